@@ -1,0 +1,95 @@
+"""Flat and two-stage hierarchical searches composed from the oracle steps.
+
+Sec. II (flat): every template of the full bank filters every segment at the
+full sample rate, threshold 4, coincidence and time slides.  Sec. III
+(hierarchical): stage 1 filters with the coarse bank at a reduced rate
+(threshold 3.5), coincides over zero lag plus a small set of long slides,
+selects coincidences with Lambda_1 >= 7, and stage 2 re-filters each selected
+segment at the full rate with the union of the fine-bank neighbourhoods
+(threshold 4), followed by coincidence and time slides.
+
+Stage-1 data: the paper re-samples to 512 Hz without saying how; reading:
+ideal decimation, i.e. the stage-1 transform is the leading N/8 bins of the
+full-rate transform of the same segment (same df), and the stage-1 PSD the
+leading bins of the full-rate PSD.
+
+A run is ``n_seg`` segments of ``n`` samples laid back to back: sample m of
+segment s has tick s * seg_ticks + m * ticks_per_sample.
+"""
+import numpy as np
+
+from .spectral import strain_fft
+from .filter import filter_bank, triggers_from_candidates
+from .coinc import timeslide_coinc
+from .followup import followup_templates
+
+
+def _concat(parts):
+    keys = parts[0].keys()
+    return {k: np.concatenate([p[k] for p in parts]) for k in keys}
+
+
+def detector_triggers(segments, psds, fs: float, f_low: float, bank, tmpl_ids_per_seg, thr: float,
+                      window_sec: float, ticks_per_second: int, decim: int = 1):
+    """Triggers of one detector over all segments.  ``decim`` > 1 filters at fs/decim."""
+    out = []
+    for s, seg in enumerate(segments):
+        n_full = len(seg)
+        n = n_full // decim
+        f = fs / decim
+        st = strain_fft(seg, fs)[: n // 2 + 1]
+        psd = psds[s][: n // 2 + 1]
+        ids = np.asarray(tmpl_ids_per_seg[s], np.int64)
+        c = filter_bank(st, psd, n, f, f_low, bank, ids, thr)
+        tps = int(round(ticks_per_second / f))
+        seg_ticks = n_full * int(round(ticks_per_second / fs))
+        tr = triggers_from_candidates(c["tpos"], c["m"], c["rho2"], c["phase"], ids,
+                                      int(round(window_sec * f)), s, s * seg_ticks, tps)
+        out.append(tr)
+    return _concat(out)
+
+
+def flat_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, bank, thr=4.0, window_sec=1.0,
+                ticks_per_second=51200, n_slides=2000, step_sec=0.1, coinc_window_sec=0.015,
+                cluster_sec=1.0, edges=(8.0,)):
+    ids = [np.arange(bank.n_tmpl)] * len(h_segments)
+    th = detector_triggers(h_segments, h_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second)
+    tl = detector_triggers(l_segments, l_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second)
+    wrap = len(h_segments) * len(h_segments[0]) * int(round(ticks_per_second / fs))
+    co = timeslide_coinc(th, tl, n_slides, int(round(step_sec * ticks_per_second)),
+                         int(round(coinc_window_sec * ticks_per_second)), wrap,
+                         int(round(cluster_sec * ticks_per_second)), np.asarray(edges, np.float32),
+                         ticks_per_second)
+    return dict(trig_h=th, trig_l=tl, coinc=co)
+
+
+def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coarse, fine,
+                        decim=4, thr1=3.5, thr2=4.0, window_sec=1.0, ticks_per_second=51200,
+                        n_sh1=16, t_sh1_sec=15.0, rho1=7.0, mc_frac=0.05,
+                        n_slides=2000, step_sec=0.1, coinc_window_sec=0.015, cluster_sec=1.0,
+                        edges=(8.0,)):
+    n_seg = len(h_segments)
+    n_full = len(h_segments[0])
+    tpt = int(round(ticks_per_second / fs))
+    seg_ticks = n_full * tpt
+    wrap = n_seg * seg_ticks
+    win = int(round(coinc_window_sec * ticks_per_second))
+    cw = int(round(cluster_sec * ticks_per_second))
+    e = np.asarray(edges, np.float32)
+    ids1 = [np.arange(coarse.n_tmpl)] * n_seg
+    t1h = detector_triggers(h_segments, h_psds, fs, f_low, coarse, ids1, thr1, window_sec,
+                            ticks_per_second, decim)
+    t1l = detector_triggers(l_segments, l_psds, fs, f_low, coarse, ids1, thr1, window_sec,
+                            ticks_per_second, decim)
+    c1 = timeslide_coinc(t1h, t1l, n_sh1, int(round(t_sh1_sec * ticks_per_second)), win, wrap, cw,
+                         e, ticks_per_second)
+    fine_ids = followup_templates(c1["coincs"], rho1, coarse.mchirp, fine.mchirp, mc_frac,
+                                  seg_ticks, n_seg)
+    t2h = detector_triggers(h_segments, h_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
+                            ticks_per_second)
+    t2l = detector_triggers(l_segments, l_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
+                            ticks_per_second)
+    c2 = timeslide_coinc(t2h, t2l, n_slides, int(round(step_sec * ticks_per_second)), win, wrap, cw,
+                         e, ticks_per_second)
+    return dict(stage1_h=t1h, stage1_l=t1l, coinc1=c1, fine_ids=fine_ids, trig_h=t2h, trig_l=t2l,
+                coinc=c2)
