@@ -1,0 +1,231 @@
+/*
+ * hs.h -- C ABI of libhs, the MI355X (gfx950) hierarchical matched-filter search.
+ *
+ * The library computes, on one GPU, the frequency-domain matched filter of a
+ * compact-binary template bank against whitened detector strain and the
+ * post-filter steps of the two-stage hierarchical search of
+ * "Obtaining Statistical Significance of Gravitational Wave Signals in
+ * Hierarchical Search" (Soni, Dhurandhar, Mitra):
+ *
+ *   hs_welch_psd        one-sided PSD S_n(f) of Eq. (2), estimated from the data
+ *   hs_whiten           data Fourier transform divided by sqrt(S_n) on the band
+ *   hs_prepare_bank     template sigma (Eq. (2) with x = y = h) and pre-whitened,
+ *                       sigma-normalised template spectra
+ *   hs_matched_filter   complex SNR series of Eq. (1)/(2), threshold (Sec. II)
+ *   hs_snr_series       the same SNR series written out in full (diagnostics)
+ *   hs_cluster_triggers peak clustering of above-threshold samples into triggers
+ *   hs_timeslide_coinc  two-detector coincidence over time slides, per-slide
+ *                       clustering, background counts for Eq. (6) (Secs. I-II)
+ *   hs_followup         stage-1 selection and union of fine-bank neighbourhoods
+ *                       (Sec. III)
+ *
+ * Conventions shared by every call
+ *  - Pointers marked "device" are HIP device pointers owned by the caller; the
+ *    library never frees caller memory.  Pointers marked "host" are ordinary
+ *    host memory.  The context owns its own scratch (grown on demand).
+ *  - All device work is enqueued on the stream given to hs_create, in order.
+ *    Calls that return a count through a host pointer synchronise that stream
+ *    before returning; the others return without synchronising.
+ *  - Every call returns an hs_status.  On failure the call leaves its outputs
+ *    unspecified (except HS_EOVERFLOW, below) and hs_last_error() describes
+ *    the failure.  Nothing is thrown across the ABI.
+ *  - HS_EOVERFLOW: a capacity-bounded output (cap records) was too small.  The
+ *    required record count is stored in the count output so the caller can
+ *    grow the buffer and call again; the records written are unspecified.
+ *  - Frequencies: df = fs / n, bin k is f_k = k df.  Complex spectra are
+ *    interleaved (re, im) float pairs ("complex64").  Data transform convention
+ *    x~[k] = dt sum_j x[j] exp(-2 pi i k j / n).
+ *  - Time is int64 "ticks" chosen by the caller; a sample of a segment at fs
+ *    spans ticks_per_sample ticks.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hs_ctx hs_ctx;
+
+typedef enum {
+    HS_OK = 0,
+    HS_EINVAL = -1,     /* invalid argument (shape, size, pointer, range) */
+    HS_ENOMEM = -2,     /* device or host allocation failed */
+    HS_EOVERFLOW = -3,  /* output capacity too small; required count returned */
+    HS_EDEVICE = -4     /* HIP runtime error */
+} hs_status;
+
+typedef enum { HS_F32 = 0, HS_BF16 = 1, HS_F16 = 2 } hs_dtype;
+
+/* One above-threshold sample of one template's SNR series.
+ * tpos = position of the template in the tmpl_ids list of the filter call,
+ * m = sample index (coalescence sample, 0..n-1), rho2 = rho^2, phase = arg z. */
+typedef struct { int32_t tpos; int32_t m; float rho2; float phase; } hs_candidate;      /* 16 B */
+
+/* A clustered single-detector trigger (Sec. II: a stored SNR peak). */
+typedef struct { int32_t seg; int32_t tmpl; int64_t tick; float snr; float phase; } hs_trigger; /* 24 B */
+
+/* A surviving coincidence of slide `slide` (0 = zero lag).  tick_l is the
+ * unshifted L tick.  stat = rho_H^2 + rho_L^2 (the value every decision uses),
+ * snr_c = sqrt(stat). */
+typedef struct {
+    int32_t slide; int32_t tmpl; int64_t tick_h; int64_t tick_l;
+    float snr_h; float snr_l; float stat; float snr_c;
+} hs_coinc;                                                                             /* 40 B */
+
+/* A prepared bank (all pointers device, owned by the caller; filled by
+ * hs_prepare_bank).  Template t's prepared spectrum for bin k lives at
+ * spectra[offset[t] + k - k0[t]] (element of `dtype`: complex64, or a pair of
+ * bf16/f16), non-zero only on the integration band [k_lo[t], k_hi[t]]. */
+typedef struct {
+    int32_t n_tmpl;
+    int32_t dtype;            /* hs_dtype */
+    int64_t n;                /* FFT length the bank was prepared for */
+    double fs;                /* sample rate the bank was prepared for */
+    const int64_t *offset;    /* [n_tmpl] */
+    const int32_t *k0;        /* [n_tmpl] first stored bin */
+    const int32_t *k_lo;      /* [n_tmpl] first band bin */
+    const int32_t *k_hi;      /* [n_tmpl] last band bin (inclusive) */
+    const void *spectra;
+    const float *rho2_scale;  /* [n_tmpl] factor applied to |z|^2 (undoes storage scaling) */
+} hs_bank;
+
+/* Context: binds a device and a HIP stream (hipStream_t; NULL = default stream). */
+int hs_create(hs_ctx **ctx, int device, void *hip_stream);
+int hs_destroy(hs_ctx *ctx);
+/* Message of the last failure on this thread ("" if none). */
+const char *hs_last_error(void);
+/* ABI version; changes whenever a struct or signature changes. */
+int hs_abi_version(void);
+
+/*
+ * One-sided Welch PSD (the weight S_n of Eq. (2); the paper does not say how
+ * it is estimated).  Segments of seg_len samples every seg_len/2 samples,
+ * periodic Hann window w[i] = 1/2 - 1/2 cos(2 pi i / seg_len), periodograms
+ * scaled by 1/(fs sum w^2), doubled for 0 < j < seg_len/2, averaged, then
+ * linearly interpolated onto f_k = k fs/n, k = 0..n/2.  Arithmetic in float64.
+ *   strain  device float  [n]
+ *   psd_out device double [n/2 + 1]
+ * Requires n, seg_len powers of two, 16 <= seg_len <= n, seg_len <= 2^16.
+ */
+int hs_welch_psd(hs_ctx *ctx, const float *strain, int64_t n, double fs, int64_t seg_len,
+                 double *psd_out);
+
+/*
+ * Whitened data spectrum d~[k] = x~[k] / sqrt(S[k]) for k_lo <= k <= n/2 - 1,
+ * zero for k < k_lo; k_lo = max(1, ceil(f_low n / fs)) (lower limit of Eq. (2)).
+ * The transform runs in float32; the division in float64.
+ *   strain   device float  [n]          n a power of two, 2^10 <= n <= 2^22
+ *   psd      device double [n/2 + 1]    positive on the band
+ *   spec_out device complex64 [n/2]     bins 0..n/2-1
+ * The leading m/2 bins of spec_out are also the whitened spectrum of the same
+ * data ideally decimated to m samples (same df), which is how a lower-rate
+ * stage reuses it.
+ */
+int hs_whiten(hs_ctx *ctx, const float *strain, int64_t n, double fs, double f_low,
+              const double *psd, void *spec_out);
+
+/*
+ * Bank preparation.  For each template t (raw spectrum h~ stored band-packed
+ * at raw[offset[t] + k - k0[t]] for k0[t] <= k <= k1[t], complex64):
+ *   k_lo = max(1, ceil(f_low n / fs), kstart[t]),  k_hi = min(k1[t], n/2 - 1)
+ *   sigma^2 = 4 df sum_{k_lo..k_hi} |h~_k|^2 / S_k            (float64)
+ *   w~_k = scale_t * 4 df h~_k / (sqrt(S_k) sigma) on the band, 0 elsewhere
+ * stored as `dtype` in spectra_out with the SAME layout as raw (offsets,
+ * k0..k1).  scale_t is 1 for HS_F32 and a power of two keeping the largest
+ * element near 2^14 for HS_BF16/HS_F16; rho2_scale_out[t] = 1/scale_t^2.
+ * With this, sum_k d~_k conj(w~_k) e^{2 pi i k m / n} / scale_t is the complex
+ * SNR z[m] of Eq. (1)/(2) (quadrature form of Appendix A).
+ *   psd device double [n/2 + 1]; raw, offset, k0, kstart, k1 device;
+ *   spectra_out device (element size 8 for F32, 4 otherwise);
+ *   k_lo_out, k_hi_out, rho2_scale_out, sigma_out device [n_tmpl].
+ * HS_EINVAL if a band is empty or k1 >= k0 is violated.
+ */
+int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, const double *psd,
+                    int32_t n_tmpl, const void *raw, const int64_t *offset, const int32_t *k0,
+                    const int32_t *kstart, const int32_t *k1, int32_t dtype, void *spectra_out,
+                    int32_t *k_lo_out, int32_t *k_hi_out, float *rho2_scale_out,
+                    double *sigma_out);
+
+/*
+ * Matched filter + threshold (Sec. II: a sample is kept when rho >= thr,
+ * compared as rho^2 >= thr^2 in float32).  For each template tmpl_ids[p]:
+ *   z[m] = sum_{k in band} spec[k] conj(w~[k]) e^{+2 pi i k m / n} / scale,  m = 0..n-1
+ * and every m with |z[m]|^2 >= thr^2 is appended to cand as {p, m, |z|^2, arg z}.
+ * Candidate order is unspecified (hs_cluster_triggers imposes one).
+ *   spec     device complex64, bins 0..n/2-1 (from hs_whiten at this n, or the
+ *            leading bins of a longer segment's spectrum with the same df)
+ *   bank     prepared at this n and fs
+ *   tmpl_ids device int32 [n_ids], each in [0, bank->n_tmpl)
+ *   cand     device hs_candidate [cap];  n_cand host: number found
+ * n must be a power of two with 2^13 <= n <= 2^20.
+ */
+int hs_matched_filter(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                      const int32_t *tmpl_ids, int32_t n_ids, float thr, hs_candidate *cand,
+                      int64_t cap, int64_t *n_cand);
+
+/* The complex SNR series z[m] of hs_matched_filter written out in full:
+ * z_out device complex64 [n_ids][n]. */
+int hs_snr_series(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                  const int32_t *tmpl_ids, int32_t n_ids, void *z_out);
+
+/*
+ * Peak clustering (Sec. II: a trigger is the peak of the SNR; rule not given,
+ * reading): candidate m of template position p survives iff every other
+ * candidate m' of p with |m' - m| <= window has rho2' < rho2, or rho2' == rho2
+ * and m' > m.  Survivors are written as triggers
+ *   {seg, tmpl_ids[p], seg_t0 + m * ticks_per_sample, sqrt(rho2), phase}
+ * sorted by (p, m).  Candidates must have distinct (tpos, m), 0 <= m < n,
+ * 0 <= tpos < n_ids.
+ *   cand device [n_cand]; tmpl_ids device [n_ids]; out device [cap]; n_out host.
+ */
+int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, int64_t n,
+                        const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int32_t seg,
+                        int64_t seg_t0, int64_t ticks_per_sample, hs_trigger *out, int64_t cap,
+                        int64_t *n_out);
+
+/*
+ * Two-detector coincidence over time slides (Sec. I; Sec. II, Eq. (6)).
+ * A pair (H trigger i, L trigger j) with the same tmpl is coincident at slide
+ * k in [0, n_slides] iff |((t_i - t_j - k step + T/2) mod T) - T/2| <= window,
+ * T = wrap.  stat = (float)((double)snr_i^2 + (double)snr_j^2) (network SNR
+ * squared, Appendix A).  Per slide, a coincidence survives iff no other of
+ * the same slide within circular |tick_h' - tick_h| <= cluster_w has a larger
+ * stat, or an equal stat and a smaller (tmpl, tick_h, tick_l).  Survivors of
+ * every slide are written to out sorted by (slide, tick_h).  bg_counts[e] =
+ * number of survivors with slide >= 1 and (double)stat >= (double)edges[e]^2.
+ *   h, l device hs_trigger [nh], [nl]; ticks in [0, wrap); tmpl in [0, n_tmpl)
+ *   edges host float [n_edges]; bg_counts host int64 [n_edges]
+ *   out device hs_coinc [cap]; n_out host
+ * Requires 0 <= 2 window < wrap, step > 0, 0 < cluster_w < 65536,
+ * n_slides >= 0.  Background time is n_slides * wrap ticks (Eq. (6) T_b).
+ */
+int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, const hs_trigger *l,
+                       int64_t nl, int32_t n_tmpl, int64_t n_slides, int64_t step,
+                       int64_t window, int64_t wrap, int64_t cluster_w, const float *edges,
+                       int32_t n_edges, int64_t *bg_counts, hs_coinc *out, int64_t cap,
+                       int64_t *n_out);
+
+/*
+ * Stage-1 follow-up (Sec. III): coincidences with (double)stat >= rho_min^2
+ * are followed; the neighbourhood of coarse template c is every fine template
+ * f with |mchirp_f - mchirp_c| <= frac * mchirp_c (float64, inclusive); a
+ * followed coincidence adds its neighbourhood to segment tick_h / seg_ticks
+ * and to segment tick_l / seg_ticks.  Row s of fine_ids (device int32
+ * [n_seg][n_fine]) receives the sorted unique fine ids of segment s, and
+ * n_ids[s] (host) their count.
+ *   c device [n_c]; coarse_mchirp device double [n_coarse];
+ *   fine_mchirp device double [n_fine]
+ */
+int hs_followup(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_min,
+                const double *coarse_mchirp, int32_t n_coarse, const double *fine_mchirp,
+                int32_t n_fine, double frac, int64_t seg_ticks, int32_t n_seg, int32_t *fine_ids,
+                int32_t *n_ids);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H */

@@ -1,0 +1,341 @@
+// Matched filter (Sec. II, Eqs. (1)-(2); quadrature form of Appendix A): for every template,
+//   z[m] = sum_{k in band} d~[k] conj(w~[k]) exp(+2 pi i k m / N),   m = 0..N-1,
+// with d~ the whitened data and w~ the prepared (whitened, sigma-normalised) template, then
+// rho^2 = |z|^2 compared against thr^2 (Sec. II: "greater than or equal to").
+//
+// The N-point inverse transform is split four-step with N = 512 * N1:
+//   k = k1 + N1 k2  (k1 < N1, k2 < 512),   m = m2 + 512 m1  (m2 < 512, m1 < N1)
+//   pass A:  Y[m2][k1] = W_N^{k1 m2} sum_{k2} q[k1 + N1 k2] W_512^{k2 m2},   q = d~ conj(w~)
+//   pass B:  z[m2 + 512 m1] = sum_{k1} Y[m2][k1] W_N1^{k1 m1}
+// (W_L = exp(+2 pi i / L)).  The data and templates only occupy k < N/2, i.e. k2 < 256, so the
+// 512-point transform of pass A is pruned to two 256-point transforms (of x[k2] and of
+// x[k2] W_512^{k2}, giving the even and odd outputs).  The product d~ conj(w~) is formed while
+// loading (only bins inside the template's band are read), and pass B ends with the threshold
+// and a wavefront-ballot compaction: one atomic per wavefront that holds candidates.
+//
+// Pass A: a 256-thread workgroup owns 16 consecutive columns k1 of one template; thread
+// (c = tid % 16, l = tid / 16) loads x[l + 16 j], j < 16, of column c (16 lanes read 128
+// contiguous bytes of spectrum per row), does a radix-16 DFT over j in registers, exchanges
+// through LDS, and a second radix-16 DFT finishes each 256-point transform.
+// Pass B: each lane holds 16 points of a row; N1/16 lanes share a row; radix-16 passes with
+// LDS exchanges (Stockham indexing), the last pass ending in registers for the epilogue.
+#include <cmath>
+
+#include "dft.h"
+#include "hs_internal.h"
+#include "storage.h"
+
+namespace hs {
+
+static constexpr int PA_LDS_LSTRIDE = 16 * 16 + 16;  // float2 per l-block (padded by 16)
+
+__global__ void mf_validate(const int32_t *__restrict__ ids, int32_t n_ids, int32_t n_tmpl,
+                            const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
+                            const int32_t *__restrict__ khi, int64_t half, int32_t *__restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_ids) return;
+    const int32_t t = ids[i];
+    if (t < 0 || t >= n_tmpl) {
+        atomicOr(bad, 1);
+        return;
+    }
+    if (klo[t] < 1 || klo[t] < k0[t] || khi[t] > half - 1) atomicOr(bad, 2);
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void mf_pass_a(
+    const float2 *__restrict__ dspec, const typename ST::elem *__restrict__ spectra,
+    const int64_t *__restrict__ offset, const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
+    const int32_t *__restrict__ khi, const int32_t *__restrict__ ids, int32_t id0, int32_t N1,
+    const float2 *__restrict__ tw512, const float2 *__restrict__ twlo, const float2 *__restrict__ twhi,
+    const int32_t *__restrict__ bad, float2 *__restrict__ Y) {
+    __shared__ float2 lds[16 * PA_LDS_LSTRIDE];
+    if (*bad) return;
+    const int tb = blockIdx.y;
+    const int t = ids[id0 + tb];
+    const int c = threadIdx.x & 15;
+    const int l = threadIdx.x >> 4;
+    const int k1 = blockIdx.x * 16 + c;
+    const int64_t base = offset[t] - k0[t];
+    const int lo = klo[t], hi = khi[t];
+
+    float2 x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int k = k1 + N1 * (l + 16 * j);
+        float2 v = float2{0.0f, 0.0f};
+        if (k >= lo && k <= hi) v = cmulc(dspec[k], ST::load(spectra, base + k));
+        x[j] = v;
+    }
+    float2 *Yt = Y + (size_t)tb * 512 * (size_t)N1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        float2 v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = r ? cmul(x[j], tw512[l + 16 * j]) : x[j];
+        dft16<1>(v);  // v[a] = sum_j x[l + 16 j] W_16^{j a}
+#pragma unroll
+        for (int a = 1; a < 16; ++a) v[a] = cmul(v[a], tw512[2 * l * a]);  // W_256^{l a}
+        if (r) __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 16; ++a) lds[l * PA_LDS_LSTRIDE + a * 16 + c] = v[a];
+        __syncthreads();
+        const int a = l;
+        float2 w[16];
+#pragma unroll
+        for (int l2 = 0; l2 < 16; ++l2) w[l2] = lds[l2 * PA_LDS_LSTRIDE + a * 16 + c];
+        dft16<1>(w);  // w[b] = 256-point output a + 16 b
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const int m2 = 2 * (a + 16 * b) + r;
+            const int jj = k1 * m2;  // < N
+            const float2 tw = cmul(twhi[jj >> 10], twlo[jj & 1023]);
+            Yt[(size_t)m2 * N1 + k1] = cmul(w[b], tw);
+        }
+    }
+}
+
+// Radix schedule of pass B: first radix 16, then R2 and R3 (1 = absent).
+template <int N1> struct PassBPlan;
+template <> struct PassBPlan<16> { static constexpr int R2 = 1, R3 = 1; };
+template <> struct PassBPlan<32> { static constexpr int R2 = 2, R3 = 1; };
+template <> struct PassBPlan<64> { static constexpr int R2 = 4, R3 = 1; };
+template <> struct PassBPlan<128> { static constexpr int R2 = 8, R3 = 1; };
+template <> struct PassBPlan<256> { static constexpr int R2 = 16, R3 = 1; };
+template <> struct PassBPlan<512> { static constexpr int R2 = 16, R3 = 2; };
+template <> struct PassBPlan<1024> { static constexpr int R2 = 16, R3 = 4; };
+template <> struct PassBPlan<2048> { static constexpr int R2 = 16, R3 = 8; };
+
+// Output index of register e after a pass with radix R at sub-transform size Ns.
+template <int LPR, int R, int Ns>
+__device__ __forceinline__ int pass_out_index(int ln, int e) {
+    const int b = e / R, r = e % R;
+    const int j = ln + LPR * b;
+    return (j / Ns) * Ns * R + (j % Ns) + r * Ns;
+}
+
+template <int N1, int LPR, int R, int Ns>
+__device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int ln) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[pass_out_index<LPR, R, Ns>(ln, e)] = v[e];
+}
+
+template <int N1, int LPR, int R, int Ns>
+__device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int ln, const float2 *tw) {
+#pragma unroll
+    for (int b = 0; b < 16 / R; ++b) {
+        const int j = ln + LPR * b;
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 x = row[j + r * (N1 / R)];
+            if (r > 0) x = cmul(x, tw[k * r * (N1 / (Ns * R))]);
+            v[b * R + r] = x;
+        }
+        dft<R, 1>(v + b * R);
+    }
+}
+
+template <int N1, bool WRITE_Z>
+__global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
+                                                 const int32_t *__restrict__ ids, int32_t id0, float thr2,
+                                                 const float2 *__restrict__ twN1, const int32_t *__restrict__ bad,
+                                                 hs_candidate *__restrict__ cand,
+                                                 unsigned long long *__restrict__ counter, int64_t cap,
+                                                 float2 *__restrict__ zout) {
+    constexpr int LPR = N1 / 16;    // lanes per row
+    constexpr int RPB = 256 / LPR;  // rows per block
+    constexpr int R2 = PassBPlan<N1>::R2, R3 = PassBPlan<N1>::R3;
+    __shared__ float2 lds[N1 > 16 ? RPB * N1 : 1];
+    if (*bad) return;
+    const int tb = blockIdx.y;
+    const int lr = threadIdx.x / LPR;
+    const int ln = threadIdx.x % LPR;
+    const int m2 = blockIdx.x * RPB + lr;
+    const float2 *src = Y + ((size_t)tb * 512 + m2) * (size_t)N1;
+
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = src[ln + r * LPR];
+    dft16<1>(v);
+    float2 *row = lds + (N1 > 16 ? lr * N1 : 0);
+    if constexpr (R2 > 1) {
+        lds_write_pass<N1, LPR, 16, 1>(row, v, ln);
+        __syncthreads();
+        lds_read_pass<N1, LPR, R2, 16>(v, row, ln, twN1);
+    }
+    if constexpr (R3 > 1) {
+        __syncthreads();
+        lds_write_pass<N1, LPR, R2, 16>(row, v, ln);
+        __syncthreads();
+        lds_read_pass<N1, LPR, R3, 16 * R2>(v, row, ln, twN1);
+    }
+    constexpr int RL = R3 > 1 ? R3 : (R2 > 1 ? R2 : 16);
+    constexpr int NsL = R3 > 1 ? 16 * R2 : (R2 > 1 ? 16 : 1);
+
+    const int t = ids[id0 + tb];
+    const float sc = r2scale[t];
+    if constexpr (WRITE_Z) {
+        const float zs = sqrtf(sc);
+        float2 *zt = zout + (size_t)(id0 + tb) * 512 * (size_t)N1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m1 = pass_out_index<LPR, RL, NsL>(ln, e);
+            zt[m2 + 512 * m1] = float2{v[e].x * zs, v[e].y * zs};
+        }
+    } else {
+        const int lane = __lane_id();
+        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float2 z = v[e];
+            const float r2 = (z.x * z.x + z.y * z.y) * sc;
+            const bool p = r2 >= thr2;
+            const unsigned long long mask = __ballot(p);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long b0 = 0;
+                if (lane == leader) b0 = atomicAdd(counter, (unsigned long long)__popcll(mask));
+                b0 = __shfl(b0, leader);
+                if (p) {
+                    const unsigned long long idx = b0 + (unsigned long long)__popcll(mask & below);
+                    if (idx < (unsigned long long)cap) {
+                        const int m1 = pass_out_index<LPR, RL, NsL>(ln, e);
+                        hs_candidate o;
+                        o.tpos = id0 + tb;
+                        o.m = m2 + 512 * m1;
+                        o.rho2 = r2;
+                        o.phase = atan2f(z.y, z.x);
+                        cand[idx] = o;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <bool WRITE_Z>
+static int launch_pass_b(hs_ctx *ctx, int N1, dim3 grid, const float2 *Y, const float *r2s, const int32_t *ids,
+                         int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
+                         unsigned long long *counter, int64_t cap, float2 *zout) {
+#define HS_PB(NN)                                                                                         \
+    case NN:                                                                                              \
+        hipLaunchKernelGGL((mf_pass_b<NN, WRITE_Z>), grid, dim3(256), 0, ctx->stream, Y, r2s, ids, id0, thr2, \
+                           twN1, bad, cand, counter, cap, zout);                                          \
+        break;
+    switch (N1) {
+        HS_PB(16) HS_PB(32) HS_PB(64) HS_PB(128) HS_PB(256) HS_PB(512) HS_PB(1024) HS_PB(2048)
+    default: return set_error(HS_EINVAL, "matched filter: unsupported N1 %d", N1);
+    }
+#undef HS_PB
+    HS_HIP(hipGetLastError());
+    return HS_OK;
+}
+
+template <bool WRITE_Z>
+static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank, const int32_t *ids,
+                  int32_t n_ids, float thr, hs_candidate *cand, int64_t cap, int64_t *n_cand, float2 *zout) {
+    HS_REQUIRE(ctx && spec && bank && (ids || n_ids == 0), "matched filter: null argument");
+    HS_REQUIRE(is_pow2(n) && n >= 8192 && n <= (int64_t(1) << 20),
+               "matched filter: n must be a power of two in [2^13, 2^20] (got %lld)", (long long)n);
+    HS_REQUIRE(bank->n == n, "matched filter: bank prepared for n=%lld, called with n=%lld", (long long)bank->n,
+               (long long)n);
+    HS_REQUIRE(bank->fs == fs, "matched filter: bank prepared for fs=%g, called with fs=%g", bank->fs, fs);
+    HS_REQUIRE(bank->offset && bank->k0 && bank->k_lo && bank->k_hi && bank->spectra && bank->rho2_scale,
+               "matched filter: bank has a null pointer");
+    HS_REQUIRE(bank->dtype == HS_F32 || bank->dtype == HS_BF16 || bank->dtype == HS_F16,
+               "matched filter: bad bank dtype");
+    HS_REQUIRE(n_ids >= 0, "matched filter: negative n_ids");
+    if (!WRITE_Z) HS_REQUIRE(cand && n_cand && cap >= 0, "matched filter: bad candidate output");
+    else HS_REQUIRE(zout != nullptr, "snr series: null output");
+    HS_HIP(hipSetDevice(ctx->device));
+    if (!WRITE_Z) *n_cand = 0;
+    if (n_ids == 0) return HS_OK;
+
+    const int log2N = ilog2(n);
+    const int N1 = (int)(n / 512);
+    const size_t per_tmpl = (size_t)n * sizeof(float2);
+    int64_t tb_max = (int64_t)(ctx->mf_batch_bytes / per_tmpl);
+    if (tb_max < 1) tb_max = 1;
+    if (tb_max > 65535) tb_max = 65535;
+    if (tb_max > n_ids) tb_max = n_ids;
+
+    const float2 *tw512, *twlo, *twhi, *twN1;
+    HS_TRY(twiddles_f32(ctx, 9, &tw512));
+    HS_TRY(twiddles_f32(ctx, log2N, &twlo));
+    HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
+    HS_TRY(twiddles_f32(ctx, ilog2(N1), &twN1));
+
+    float2 *Y;
+    unsigned long long *counter;
+    int32_t *bad;
+    Carver cv;
+    cv.add(&Y, (size_t)tb_max * n);
+    cv.add(&counter, 1);
+    cv.add(&bad, 1);
+    HS_TRY(cv.commit(ctx));
+    HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), 1, 0));
+    HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
+    hipLaunchKernelGGL(mf_validate, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
+                       bank->n_tmpl, bank->k0, bank->k_lo, bank->k_hi, n / 2, bad);
+    HS_HIP(hipGetLastError());
+
+    const float thr2 = thr * thr;
+    for (int64_t id0 = 0; id0 < n_ids; id0 += tb_max) {
+        const int32_t tb = (int32_t)((n_ids - id0) < tb_max ? (n_ids - id0) : tb_max);
+        const dim3 ga((unsigned)(N1 / 16), (unsigned)tb);
+        const float2 *d = static_cast<const float2 *>(spec);
+        switch (bank->dtype) {
+        case HS_F32:
+            hipLaunchKernelGGL(mf_pass_a<StoreF32>, ga, dim3(256), 0, ctx->stream, d,
+                               static_cast<const float2 *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+            break;
+        case HS_BF16:
+            hipLaunchKernelGGL(mf_pass_a<StoreBF16>, ga, dim3(256), 0, ctx->stream, d,
+                               static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+            break;
+        default:
+            hipLaunchKernelGGL(mf_pass_a<StoreF16>, ga, dim3(256), 0, ctx->stream, d,
+                               static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+            break;
+        }
+        HS_HIP(hipGetLastError());
+        const dim3 gb((unsigned)(N1 / 8), (unsigned)tb);
+        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, gb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, cand,
+                                      counter, cap, zout));
+    }
+    struct {
+        unsigned long long count;
+        int32_t bad;
+    } h{};
+    HS_TRY(read_back(ctx, counter, &h.count, sizeof(h.count)));
+    HS_TRY(read_back(ctx, bad, &h.bad, sizeof(h.bad)));
+    HS_REQUIRE(h.bad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
+               h.bad);
+    if (!WRITE_Z) {
+        *n_cand = (int64_t)h.count;
+        if ((int64_t)h.count > cap)
+            return set_error(HS_EOVERFLOW, "matched filter: %llu candidates exceed capacity %lld", h.count,
+                             (long long)cap);
+    }
+    return HS_OK;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" int hs_matched_filter(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                                 const int32_t *tmpl_ids, int32_t n_ids, float thr, hs_candidate *cand, int64_t cap,
+                                 int64_t *n_cand) {
+    return run_mf<false>(ctx, spec, n, fs, bank, tmpl_ids, n_ids, thr, cand, cap, n_cand, nullptr);
+}
+
+extern "C" int hs_snr_series(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                             const int32_t *tmpl_ids, int32_t n_ids, void *z_out) {
+    return run_mf<true>(ctx, spec, n, fs, bank, tmpl_ids, n_ids, 0.0f, nullptr, 0, nullptr,
+                        static_cast<float2 *>(z_out));
+}

@@ -1,0 +1,321 @@
+"""Thin ctypes binding of libhs (``include/hs.h``): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device buffers are
+PyTorch tensors (memory and streams only); all computation happens in the HIP
+kernels of libhs.  If the shared library is missing the import fails loudly --
+there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhs.so")
+
+HS_OK, HS_EINVAL, HS_ENOMEM, HS_EOVERFLOW, HS_EDEVICE = 0, -1, -2, -3, -4
+HS_F32, HS_BF16, HS_F16 = 0, 1, 2
+DTYPES = {"f32": HS_F32, "bf16": HS_BF16, "f16": HS_F16}
+ELEM_BYTES = {HS_F32: 8, HS_BF16: 4, HS_F16: 4}
+
+CANDIDATE = np.dtype([("tpos", "<i4"), ("m", "<i4"), ("rho2", "<f4"), ("phase", "<f4")])
+TRIGGER = np.dtype([("seg", "<i4"), ("tmpl", "<i4"), ("tick", "<i8"), ("snr", "<f4"), ("phase", "<f4")])
+COINC = np.dtype([("slide", "<i4"), ("tmpl", "<i4"), ("tick_h", "<i8"), ("tick_l", "<i8"),
+                  ("snr_h", "<f4"), ("snr_l", "<f4"), ("stat", "<f4"), ("snr_c", "<f4")])
+EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_welch_psd", "hs_whiten",
+           "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
+           "hs_timeslide_coinc", "hs_followup"]
+
+
+class HsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Bank(ctypes.Structure):
+    _fields_ = [("n_tmpl", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("fs", ctypes.c_double), ("offset", ctypes.c_void_p), ("k0", ctypes.c_void_p),
+                ("k_lo", ctypes.c_void_p), ("k_hi", ctypes.c_void_p), ("spectra", ctypes.c_void_p),
+                ("rho2_scale", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libhs.so not found at {path}: build it with `python -m paper_2309_00019_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    sig = {
+        "hs_create": [ctypes.POINTER(P), ctypes.c_int, P],
+        "hs_destroy": [P],
+        "hs_last_error": [],
+        "hs_abi_version": [],
+        "hs_welch_psd": [P, P, I64, D, I64, P],
+        "hs_whiten": [P, P, I64, D, D, P, P],
+        "hs_prepare_bank": [P, I64, D, D, P, I32, P, P, P, P, P, I32, P, P, P, P, P],
+        "hs_matched_filter": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
+        "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
+        "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
+        "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, P, I32, P, P, I64,
+                               ctypes.POINTER(I64)],
+        "hs_followup": [P, P, I64, F, P, I32, P, I32, D, I64, I32, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "hs_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, what=""):
+    if status != HS_OK:
+        msg = _lib.hs_last_error().decode(errors="replace")
+        raise HsError(status, f"{what}: {msg}" if what else msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(int(t))
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """hs_ctx bound to one device and the current (or given) torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(_lib.hs_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream)), "hs_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.hs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PreparedBank:
+    """Device arrays of a prepared bank (see hs_bank in hs.h)."""
+
+    def __init__(self, n, fs, dtype, offset, k0, k_lo, k_hi, spectra, rho2_scale, sigma, mchirp=None):
+        self.n, self.fs, self.dtype = int(n), float(fs), int(dtype)
+        self.offset, self.k0, self.k_lo, self.k_hi = offset, k0, k_lo, k_hi
+        self.spectra, self.rho2_scale, self.sigma, self.mchirp = spectra, rho2_scale, sigma, mchirp
+
+    @property
+    def n_tmpl(self):
+        return int(self.offset.numel())
+
+    def struct(self) -> _Bank:
+        return _Bank(self.n_tmpl, self.dtype, self.n, self.fs, _ptr(self.offset), _ptr(self.k0),
+                     _ptr(self.k_lo), _ptr(self.k_hi), _ptr(self.spectra), _ptr(self.rho2_scale))
+
+    @staticmethod
+    def allocate(n, fs, dtype, offset, k0, total_elems, device):
+        """Empty bank with the given layout (offset/k0 host arrays)."""
+        T = len(offset)
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        spectra = torch.empty(int(total_elems) * ELEM_BYTES[dt], dtype=torch.uint8, device=device)
+        return PreparedBank(n, fs, dt,
+                            torch.as_tensor(np.asarray(offset, np.int64), device=device),
+                            torch.as_tensor(np.asarray(k0, np.int32), device=device),
+                            torch.empty(T, dtype=torch.int32, device=device),
+                            torch.empty(T, dtype=torch.int32, device=device),
+                            spectra,
+                            torch.empty(T, dtype=torch.float32, device=device),
+                            torch.empty(T, dtype=torch.float64, device=device))
+
+
+def hs_abi_version() -> int:
+    return load_library().hs_abi_version()
+
+
+def hs_welch_psd(ctx: Context, strain, fs: float, seg_len: int, out=None):
+    _dev(strain, torch.float32, "strain")
+    n = strain.numel()
+    out = torch.empty(n // 2 + 1, dtype=torch.float64, device=strain.device) if out is None else out
+    _dev(out, torch.float64, "psd_out")
+    _check(_lib.hs_welch_psd(ctx.handle, _ptr(strain), n, fs, seg_len, _ptr(out)), "hs_welch_psd")
+    return out
+
+
+def hs_whiten(ctx: Context, strain, fs: float, f_low: float, psd, out=None):
+    _dev(strain, torch.float32, "strain")
+    _dev(psd, torch.float64, "psd")
+    n = strain.numel()
+    if psd.numel() < n // 2 + 1:
+        raise ValueError("psd must have n/2+1 bins")
+    out = torch.empty(n // 2, dtype=torch.complex64, device=strain.device) if out is None else out
+    _dev(out, torch.complex64, "spec_out")
+    _check(_lib.hs_whiten(ctx.handle, _ptr(strain), n, fs, f_low, _ptr(psd), _ptr(out)), "hs_whiten")
+    return out
+
+
+def hs_prepare_bank(ctx: Context, n: int, fs: float, f_low: float, psd, raw, offset, k0, kstart, k1,
+                    dtype="f32", bank: PreparedBank = None, t0: int = 0, elem0: int = 0):
+    """Prepare templates into ``bank`` (allocated with the same layout as ``raw``).
+
+    ``raw`` complex64 device tensor; offset/k0/kstart/k1 device tensors relative to ``raw``.
+    With ``bank`` given, the templates land at template index ``t0`` and spectra element
+    ``elem0`` of that bank (chunked preparation of a large bank).
+    """
+    _dev(psd, torch.float64, "psd")
+    _dev(raw, torch.complex64, "raw")
+    T = offset.numel()
+    if bank is None:
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        bank = PreparedBank(n, fs, dt, offset.clone(), k0.clone(),
+                            torch.empty(T, dtype=torch.int32, device=raw.device),
+                            torch.empty(T, dtype=torch.int32, device=raw.device),
+                            torch.empty(raw.numel() * ELEM_BYTES[dt], dtype=torch.uint8, device=raw.device),
+                            torch.empty(T, dtype=torch.float32, device=raw.device),
+                            torch.empty(T, dtype=torch.float64, device=raw.device))
+    eb = ELEM_BYTES[bank.dtype]
+    sp = bank.spectra.data_ptr() + elem0 * eb
+    _check(_lib.hs_prepare_bank(ctx.handle, n, fs, f_low, _ptr(psd), T, _ptr(raw), _ptr(offset), _ptr(k0),
+                                _ptr(kstart), _ptr(k1), bank.dtype, ctypes.c_void_p(sp),
+                                ctypes.c_void_p(bank.k_lo.data_ptr() + 4 * t0),
+                                ctypes.c_void_p(bank.k_hi.data_ptr() + 4 * t0),
+                                ctypes.c_void_p(bank.rho2_scale.data_ptr() + 4 * t0),
+                                ctypes.c_void_p(bank.sigma.data_ptr() + 8 * t0)), "hs_prepare_bank")
+    return bank
+
+
+def hs_matched_filter(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, tmpl_ids, thr: float,
+                      cap: int = None, cand=None):
+    """Returns an int32 [n_cand, 4] device tensor of hs_candidate records (view with as_records)."""
+    _dev(spec, torch.complex64, "spec")
+    _dev(tmpl_ids, torch.int32, "tmpl_ids")
+    n_ids = tmpl_ids.numel()
+    if cap is None:
+        # Rayleigh tail e^{-thr^2/2} per sample, with head-room for loud glitches
+        cap = int(n_ids * n * min(1.0, 8.0 * np.exp(-thr * thr / 2.0))) + 65536
+    bs = bank.struct()
+    for _ in range(2):
+        if cand is None or cand.shape[0] < cap:
+            cand = torch.empty((cap, 4), dtype=torch.int32, device=spec.device)
+        cnt = ctypes.c_int64(0)
+        st = _lib.hs_matched_filter(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(tmpl_ids), n_ids,
+                                    float(thr), _ptr(cand), cand.shape[0], ctypes.byref(cnt))
+        if st == HS_EOVERFLOW:
+            cap = int(cnt.value)
+            cand = None
+            continue
+        _check(st, "hs_matched_filter")
+        return cand[: cnt.value]
+    raise HsError(HS_EOVERFLOW, "hs_matched_filter: overflow after resize")
+
+
+def hs_snr_series(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, tmpl_ids, out=None):
+    _dev(spec, torch.complex64, "spec")
+    _dev(tmpl_ids, torch.int32, "tmpl_ids")
+    n_ids = tmpl_ids.numel()
+    out = torch.empty((n_ids, n), dtype=torch.complex64, device=spec.device) if out is None else out
+    bs = bank.struct()
+    _check(_lib.hs_snr_series(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(tmpl_ids), n_ids, _ptr(out)),
+           "hs_snr_series")
+    return out
+
+
+def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: int = 0, seg_t0: int = 0,
+                        ticks_per_sample: int = 1, cap: int = None):
+    """Returns an int32 [n_trig, 6] device tensor of hs_trigger records."""
+    _dev(cand, torch.int32, "cand")
+    _dev(tmpl_ids, torch.int32, "tmpl_ids")
+    n_cand = cand.shape[0]
+    if cap is None:
+        cap = min(n_cand, tmpl_ids.numel() * (n // max(window, 1) + 2)) + 16
+    for _ in range(2):
+        out = torch.empty((max(cap, 1), 6), dtype=torch.int32, device=cand.device)
+        cnt = ctypes.c_int64(0)
+        st = _lib.hs_cluster_triggers(ctx.handle, _ptr(cand), n_cand, n, _ptr(tmpl_ids), tmpl_ids.numel(), window,
+                                      seg, seg_t0, ticks_per_sample, _ptr(out), cap, ctypes.byref(cnt))
+        if st == HS_EOVERFLOW:
+            cap = int(cnt.value)
+            continue
+        _check(st, "hs_cluster_triggers")
+        return out[: cnt.value]
+    raise HsError(HS_EOVERFLOW, "hs_cluster_triggers: overflow after resize")
+
+
+def hs_timeslide_coinc(ctx: Context, trig_h, trig_l, n_tmpl: int, n_slides: int, step: int, window: int,
+                       wrap: int, cluster_w: int, edges, cap: int = None):
+    """Returns (int32 [n, 10] device tensor of hs_coinc records, int64 numpy background counts)."""
+    _dev(trig_h, torch.int32, "trig_h")
+    _dev(trig_l, torch.int32, "trig_l")
+    edges = np.ascontiguousarray(edges, dtype=np.float32)
+    bg = np.zeros(len(edges), np.int64)
+    if cap is None:
+        cap = (n_slides + 1) * (wrap // cluster_w + 2)
+    for _ in range(2):
+        out = torch.empty((max(cap, 1), 10), dtype=torch.int32, device=trig_h.device)
+        cnt = ctypes.c_int64(0)
+        st = _lib.hs_timeslide_coinc(ctx.handle, _ptr(trig_h), trig_h.shape[0], _ptr(trig_l), trig_l.shape[0],
+                                     n_tmpl, n_slides, step, window, wrap, cluster_w, _ptr(edges), len(edges),
+                                     _ptr(bg), _ptr(out), cap, ctypes.byref(cnt))
+        if st == HS_EOVERFLOW:
+            cap = int(cnt.value)
+            continue
+        _check(st, "hs_timeslide_coinc")
+        return out[: cnt.value], bg
+    raise HsError(HS_EOVERFLOW, "hs_timeslide_coinc: overflow after resize")
+
+
+def hs_followup(ctx: Context, coincs, rho_min: float, coarse_mchirp, fine_mchirp, frac: float, seg_ticks: int,
+                n_seg: int):
+    """Returns (int32 [n_seg, n_fine] device tensor, host list of per-segment counts)."""
+    _dev(coincs, torch.int32, "coincs")
+    _dev(coarse_mchirp, torch.float64, "coarse_mchirp")
+    _dev(fine_mchirp, torch.float64, "fine_mchirp")
+    n_fine = fine_mchirp.numel()
+    ids = torch.empty((n_seg, n_fine), dtype=torch.int32, device=coincs.device)
+    counts = np.zeros(n_seg, np.int32)
+    _check(_lib.hs_followup(ctx.handle, _ptr(coincs), coincs.shape[0], float(rho_min), _ptr(coarse_mchirp),
+                            coarse_mchirp.numel(), _ptr(fine_mchirp), n_fine, float(frac), seg_ticks, n_seg,
+                            _ptr(ids), _ptr(counts)), "hs_followup")
+    return ids, counts.tolist()
+
+
+def as_records(t, dtype) -> np.ndarray:
+    """Copy a device record tensor to a numpy structured array."""
+    a = t.detach().cpu().contiguous().numpy()
+    return a.view(np.uint8).reshape(-1).view(dtype)
+
+
+def to_device_records(rec: np.ndarray, device) -> torch.Tensor:
+    """Upload a numpy structured array of 4-byte-multiple records as an int32 [n, k] tensor."""
+    rec = np.ascontiguousarray(rec)
+    k = rec.dtype.itemsize // 4
+    raw = rec.view(np.uint8).reshape(-1).view(np.int32).reshape(len(rec), k)
+    return torch.as_tensor(raw.copy(), device=device)

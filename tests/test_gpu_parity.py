@@ -1,0 +1,309 @@
+"""GPU parity: every libhs entry point against the FP64 oracle on the same seeded inputs.
+
+Floating-point results follow the tolerance rule in ``helpers`` (rho within 1e-4 relative
+for FP32 storage); integer and index work (clustering, coincidence, follow-up) is compared
+bit-exactly on identical inputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import DELTA, analytic_psd, check_candidates, device_bank
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2309_00019_amd import hs
+    c = hs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _strain(cfg, det, n, fs, f_low, **kw):
+    s, _ = synth.make_strain(cfg, det, 0, n, fs, f_low, **kw)
+    return s
+
+
+# ------------------------------------------------------------------------------------------
+# a1: whitening and Welch PSD
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,fs,f_low", [(2 ** 13, 512.0, 30.0), (2 ** 16, 2048.0, 20.0), (2 ** 19, 2048.0, 20.0)])
+def test_whiten_matches_oracle(ctx, n, fs, f_low):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"whiten n={n}")
+    s = _strain(11, 0, n, fs, f_low, glitch_rate=0.05)
+    psd = analytic_psd(n, fs)
+    d = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low,
+                     torch.as_tensor(psd, device=ctx.device)).cpu().numpy()
+    ref = oracle.whitened_spectrum(s, fs, f_low, psd)
+    rms = np.sqrt(np.mean(np.abs(ref[ref != 0]) ** 2))
+    assert np.max(np.abs(d - ref)) <= 2e-5 * rms
+    k_lo = oracle.lowest_bin(n, fs, f_low)
+    assert np.all(d[:k_lo] == 0)
+
+
+@pytest.mark.parametrize("n,fs,L", [(2 ** 15, 512.0, 1024), (2 ** 19, 2048.0, 8192)])
+def test_welch_matches_oracle(ctx, n, fs, L):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"welch n={n} L={L}")
+    s = _strain(12, 0, n, fs, 20.0)
+    p = hs.hs_welch_psd(ctx, torch.as_tensor(s, device=ctx.device), fs, L).cpu().numpy()
+    ref = oracle.psd_on_grid(oracle.welch_psd(s.astype(np.float64), fs, L), fs, L, n)
+    assert np.allclose(p, ref, rtol=1e-9, atol=0)
+
+
+# ------------------------------------------------------------------------------------------
+# a2: bank preparation
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_prepare_bank_sigma_and_band(ctx, dtype):
+    import torch
+    _say(f"prepare_bank {dtype}")
+    n, fs, f_low = 2 ** 15, 2048.0, 20.0
+    m1, m2 = synth.bank_by_tau0(12, 1.4, 10.0, 1.0, 4.0, synth.rng(13, 0, 0, synth.BANK))
+    bank = synth.taylorf2_bank(m1, m2, n, fs, f_low)
+    psd = analytic_psd(n, fs)
+    pb = device_bank(ctx, bank, torch.as_tensor(psd, device=ctx.device), f_low, dtype)
+    sig = pb.sigma.cpu().numpy()
+    klo, khi = pb.k_lo.cpu().numpy(), pb.k_hi.cpu().numpy()
+    for t in range(bank.n_tmpl):
+        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        assert (klo[t], khi[t]) == (a, b)
+        ref = oracle.template_sigma(bank.spectrum(t), psd, n, fs, a, b)
+        assert abs(sig[t] / ref - 1) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# a3: complex SNR series (full) against the oracle
+# ------------------------------------------------------------------------------------------
+CASES = [
+    (2 ** 13, 512.0, 30.0, "eq"),     # the 8 equal-mass templates of the 16 s, 512 Hz case
+    (2 ** 14, 2048.0, 20.0, "tau"),
+    (2 ** 16, 2048.0, 20.0, "tau"),
+    (2 ** 17, 512.0, 20.0, "tau"),
+    (2 ** 18, 1024.0, 20.0, "tau"),
+]
+
+
+def _bank_for(kind, n, fs, f_low, count=6, seed=14):
+    if kind == "eq":
+        m1, m2 = synth.equal_mass_bank(np.arange(8.0, 16.0))
+    else:
+        T = n / fs
+        mc_lo = 1.4 if T >= 128 else 4.0
+        m1, m2 = synth.bank_by_tau0(count, mc_lo, 10.0, 1.0, 4.0, synth.rng(seed, 0, 0, synth.BANK))
+    return synth.taylorf2_bank(m1, m2, n, fs, f_low)
+
+
+@pytest.mark.parametrize("n,fs,f_low,kind", CASES)
+def test_snr_series_matches_oracle(ctx, n, fs, f_low, kind):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"snr_series n={n} fs={fs}")
+    bank = _bank_for(kind, n, fs, f_low)
+    inj = dict(m1=bank.m1[2], m2=bank.m2[2], t_c=0.37 * n / fs, phi_c=1.1, snr=15.0)
+    s = _strain(15, 0, n, fs, f_low, injections=[inj])
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
+    z = hs.hs_snr_series(ctx, spec, n, fs, pb, ids).cpu().numpy()
+    st = oracle.strain_fft(s, fs)
+    for t in range(bank.n_tmpl):
+        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        ref = oracle.snr_series(st, bank.spectrum(t), psd, n, fs, a, b)
+        err = np.max(np.abs(z[t] - ref))
+        assert err <= 2e-5 * max(1.0, np.max(np.abs(ref))), (t, err)
+        if t == 2:
+            assert int(np.argmax(np.abs(z[t]))) == int(np.argmax(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n,fs,f_low,kind", CASES)
+def test_matched_filter_candidates_follow_tolerance_rule(ctx, n, fs, f_low, kind):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"matched_filter n={n}")
+    thr = 3.5
+    bank = _bank_for(kind, n, fs, f_low, count=9, seed=16)
+    s = _strain(16, 1, n, fs, f_low, glitch_rate=0.1)
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids_h = np.arange(bank.n_tmpl - 1, -1, -1, dtype=np.int32)  # reversed: tpos != tmpl
+    ids = torch.as_tensor(ids_h, device=ctx.device)
+    cand = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, thr), hs.CANDIDATE)
+    st = oracle.strain_fft(s, fs)
+    worst = 0.0
+    for p, t in enumerate(ids_h):
+        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        ref = oracle.snr_series(st, bank.spectrum(t), psd, n, fs, a, b)
+        sel = cand["tpos"] == p
+        worst = max(worst, check_candidates(cand["m"][sel], cand["rho2"][sel], ref, thr, DELTA["f32"]))
+        ph = cand["phase"][sel]
+        ref_ph = np.angle(ref[cand["m"][sel]])
+        dphi = np.angle(np.exp(1j * (ph - ref_ph)))
+        assert np.all(np.abs(dphi) < 1e-3)
+    assert worst < DELTA["f32"]
+
+
+# ------------------------------------------------------------------------------------------
+# a4: clustering (identical candidate inputs -> exact)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,n,W", [(0, 8192, 512), (1, 2 ** 17, 512), (2, 2 ** 19, 2048), (3, 10000, 333)])
+def test_cluster_exact_on_identical_inputs(ctx, seed, n, W):
+    from paper_2309_00019_amd import hs
+    import torch
+    _say(f"cluster seed={seed}")
+    g = np.random.default_rng(seed)
+    n_t = 7
+    cand = synth.synthetic_candidates(g, n_t, n, 300, 4.0, clumps=3, clump_len=3 * W, ties=20)
+    ids_h = np.asarray(g.permutation(100)[:n_t], np.int32)
+    out = hs.hs_cluster_triggers(ctx, hs.to_device_records(cand, ctx.device), n,
+                                 torch.as_tensor(ids_h, device=ctx.device), W, seg=3, seg_t0=1000,
+                                 ticks_per_sample=25)
+    got = hs.as_records(out, hs.TRIGGER)
+    ref = oracle.triggers_from_candidates(cand["tpos"], cand["m"], cand["rho2"], cand["phase"], ids_h, W, 3,
+                                          1000, 25)
+    assert len(got) == len(ref["tick"])
+    assert np.array_equal(got["tmpl"], ref["tmpl"])
+    assert np.array_equal(got["tick"], ref["tick"])
+    assert np.all(got["seg"] == 3)
+    assert np.array_equal(got["snr"], ref["snr"].astype(np.float32))
+    assert np.array_equal(got["phase"], ref["phase"].astype(np.float32))
+
+
+# ------------------------------------------------------------------------------------------
+# a6: coincidence (identical trigger inputs -> exact)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,wrap,K,step,window,cw", [
+    (0, 20000, 12, 1000, 150, 700),
+    (1, 13107200, 2000, 5120, 768, 51200),      # 256 s, 2000 slides of 0.1 s, 15 ms window
+    (2, 30001, 40, 700, 200, 2500),             # wrap not a multiple of the clustering window
+    (3, 9000, 30, 1000, 100, 4000),             # 2 cw + 1 > wrap/2: few tiles
+])
+def test_timeslide_coinc_exact_on_identical_inputs(ctx, seed, wrap, K, step, window, cw):
+    from paper_2309_00019_amd import hs
+    _say(f"coinc seed={seed}")
+    g = np.random.default_rng(200 + seed)
+    n_tmpl = 30
+    per = 40 if wrap > 10 ** 6 else 8
+    th = synth.synthetic_triggers(g, n_tmpl, wrap, per, 25, wrap)
+    tl = synth.synthetic_triggers(g, n_tmpl, wrap, per, 25, wrap)
+    tl["snr"][::5] = th["snr"][0]  # exact stat ties
+    edges = np.array([5.0, 7.0, 8.0, 9.0, 10.0, 12.0, 14.0], np.float32)
+    out, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(th, ctx.device), hs.to_device_records(tl, ctx.device),
+                                    n_tmpl, K, step, window, wrap, cw, edges)
+    got = hs.as_records(out, hs.COINC)
+    ref = oracle.timeslide_coinc(dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"]),
+                                 dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"]),
+                                 K, step, window, wrap, cw, edges, 51200)
+    c = ref["coincs"]
+    assert len(got) == len(c["slide"]) > 0
+    for f in ("slide", "tmpl", "tick_h", "tick_l"):
+        assert np.array_equal(got[f], np.asarray(c[f]).astype(got[f].dtype)), f
+    assert np.array_equal(got["stat"], c["stat"])
+    assert np.array_equal(got["snr_h"], c["snr_h"]) and np.array_equal(got["snr_l"], c["snr_l"])
+    assert np.array_equal(bg, ref["bg_counts"])
+
+
+# ------------------------------------------------------------------------------------------
+# a5: follow-up (identical inputs -> exact)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,n_seg", [(0, 1), (1, 4)])
+def test_followup_exact(ctx, seed, n_seg):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"followup seed={seed}")
+    g = np.random.default_rng(300 + seed)
+    coarse = np.sort(g.uniform(1.4, 10, 150))
+    fine = np.sort(g.uniform(1.4, 10, 3000))
+    seg_ticks = 13107200
+    co = synth.synthetic_coincs(g, 400, 150, seg_ticks * n_seg, seg_ticks, 16, stat=(10.0, 80.0))
+    ids, counts = hs.hs_followup(ctx, hs.to_device_records(co, ctx.device), 7.0,
+                                 torch.as_tensor(coarse, device=ctx.device), torch.as_tensor(fine, device=ctx.device),
+                                 0.05, seg_ticks, n_seg)
+    ref = oracle.followup_templates(co, 7.0, coarse, fine, 0.05, seg_ticks, n_seg)
+    ids = ids.cpu().numpy()
+    for s in range(n_seg):
+        assert counts[s] == len(ref[s])
+        assert np.array_equal(ids[s, :counts[s]], ref[s])
+
+
+# ------------------------------------------------------------------------------------------
+# Edge cases and error paths
+# ------------------------------------------------------------------------------------------
+def test_empty_inputs(ctx):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("empty inputs")
+    n, fs, f_low = 2 ** 13, 512.0, 30.0
+    bank = _bank_for("eq", n, fs, f_low)
+    psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = torch.zeros(n // 2, dtype=torch.complex64, device=ctx.device)
+    ids = torch.zeros(0, dtype=torch.int32, device=ctx.device)
+    assert hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 4.0).shape[0] == 0
+    # all-zero data: no candidates at all
+    ids = torch.arange(8, dtype=torch.int32, device=ctx.device)
+    c = hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 1e-3)
+    assert c.shape[0] == 0
+    empty = torch.zeros((0, 4), dtype=torch.int32, device=ctx.device)
+    assert hs.hs_cluster_triggers(ctx, empty, n, ids, 512).shape[0] == 0
+    te = torch.zeros((0, 6), dtype=torch.int32, device=ctx.device)
+    out, bg = hs.hs_timeslide_coinc(ctx, te, te, 8, 10, 100, 10, 10000, 500, [5.0])
+    assert out.shape[0] == 0 and bg.tolist() == [0]
+
+
+def test_overflow_reports_required_count(ctx):
+    import ctypes
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("overflow")
+    n, fs, f_low = 2 ** 13, 512.0, 30.0
+    bank = _bank_for("eq", n, fs, f_low)
+    psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    s = _strain(17, 0, n, fs, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(8, dtype=torch.int32, device=ctx.device)
+    full = hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 2.0)
+    assert full.shape[0] > 10
+    buf = torch.empty((4, 4), dtype=torch.int32, device=ctx.device)
+    cnt = ctypes.c_int64(0)
+    bs = pb.struct()
+    st = hs._lib.hs_matched_filter(ctx.handle, hs._ptr(spec), n, fs, ctypes.byref(bs), hs._ptr(ids), 8,
+                                   ctypes.c_float(2.0), hs._ptr(buf), 4, ctypes.byref(cnt))
+    assert st == hs.HS_EOVERFLOW and cnt.value == full.shape[0]
+
+
+def test_invalid_template_ids_are_rejected(ctx):
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("invalid ids")
+    n, fs, f_low = 2 ** 13, 512.0, 30.0
+    bank = _bank_for("eq", n, fs, f_low)
+    psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = torch.zeros(n // 2, dtype=torch.complex64, device=ctx.device)
+    bad = torch.tensor([0, 8], dtype=torch.int32, device=ctx.device)
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_matched_filter(ctx, spec, n, fs, pb, bad, 4.0)
+    assert e.value.status == hs.HS_EINVAL
+    with pytest.raises(hs.HsError):
+        hs.hs_matched_filter(ctx, spec, 2 ** 12, fs, pb, bad[:1], 4.0)
