@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-detector hierarchical matched-filter search on one MI355X.
+
+Workload (synthetic stand-in for the paper's O3 runs, which are not available): two detectors
+x 256 s at 2048 Hz of coloured Gaussian noise from the analytic aLIGO-like PSD fit with
+sine-Gaussian glitches (0.05/s, Q = 9, f0 40-300 Hz, SNR 6-50) and TaylorF2 injections
+(network SNR 6-20); coarse bank 1,500 templates at 512 Hz and fine bank 30,000 templates at
+2048 Hz (chirp mass 1.4-10, q 1-4, uniform in tau0); background from 2,000 slides of 0.1 s,
+coincidence window 15 ms.
+
+One timed step = the whole hot path on that input with everything resident in HBM:
+Welch PSD + whitening of both detectors, stage 1 (coarse bank at 512 Hz, threshold 3.5),
+trigger clustering, stage-1 coincidence (zero lag + 16 slides of 15 s), follow-up (network
+SNR >= 7, +-5 % chirp-mass neighbourhoods), stage 2 (neighbourhood union at 2048 Hz,
+threshold 4), clustering, and the 2,000-slide coincidence with background counts.
+The plain flat search (every fine template on both detectors) is timed the same way as the
+comparator.  Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "template-seconds filtered/s on 1 GPU, hierarchical+MLP vs flat, @≤1% missed inj"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fine", type=int, default=30000)
+    ap.add_argument("--coarse", type=int, default=1500)
+    ap.add_argument("--seconds", type=int, default=256)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--injections", type=int, default=16, help="injections per detector segment")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-flat", action="store_true")
+    ap.add_argument("--chunk", type=int, default=2048, help="templates generated per host chunk")
+    ap.add_argument("--only", choices=["both", "hier", "flat"], default="both",
+                    help="restrict the run (profiling); the JSON line needs the hierarchical path")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
+    return ap.parse_args()
+
+
+def make_banks(ctx, hs, synth, n, fs, f_low, m1, m2, psds, dtype, chunk):
+    """Generate TaylorF2 spectra on the host in chunks and prepare one bank per PSD on the device."""
+    import torch
+    from synth.bank import bank_layout
+    k0, kstart, k1, offset, total = bank_layout(m1, m2, n, fs, f_low)
+    banks = [hs.PreparedBank.allocate(n, fs, dtype, offset, k0, total, ctx.device) for _ in psds]
+    T = len(m1)
+    for t0 in range(0, T, chunk):
+        t1 = min(T, t0 + chunk)
+        b = synth.taylorf2_bank(m1[t0:t1], m2[t0:t1], n, fs, f_low)
+        raw = torch.as_tensor(b.data).to(ctx.device)
+        off = torch.as_tensor(b.offset, device=ctx.device)
+        kk0 = torch.as_tensor(b.k0, device=ctx.device)
+        kks = torch.as_tensor(b.kstart, device=ctx.device)
+        kk1 = torch.as_tensor(b.k1, device=ctx.device)
+        for bank, psd in zip(banks, psds):
+            hs.hs_prepare_bank(ctx, n, fs, f_low, psd, raw, off, kk0, kks, kk1, dtype, bank=bank, t0=t0,
+                               elem0=int(offset[t0]))
+        del raw
+    mc = torch.as_tensor(synth.mchirp_eta(m1, m2)[0], device=ctx.device)
+    for bank in banks:
+        bank.mchirp = mc
+    return banks
+
+
+def mf_bytes(units, hs):
+    """Algorithmic HBM bytes of the matched-filter calls: per template, its band of template
+    spectrum (element bytes) and of whitened data (8 B) read once, plus the N-point complex64
+    intermediate written by pass A and read by pass B (16 N bytes)."""
+    total = 0
+    for n, ids, bank in units:
+        kl = bank.k_lo[ids.long()].to(dtype=__import__("torch").int64)
+        kh = bank.k_hi[ids.long()].to(dtype=__import__("torch").int64)
+        K = int((kh - kl + 1).sum().item())
+        total += K * (hs.ELEM_BYTES[bank.dtype] + 8) + 16 * n * ids.numel()
+    return total
+
+
+def found_injections(coincs_rec, inj_ticks, tol_ticks, snr_c_min=8.0):
+    zl = coincs_rec[(coincs_rec["slide"] == 0) & (coincs_rec["snr_c"] >= snr_c_min)]
+    found = 0
+    for t in inj_ticks:
+        if np.any(np.abs(zl["tick_h"] - t) <= tol_ticks):
+            found += 1
+    return found
+
+
+def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2):
+    """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores)."""
+    import oracle
+    L = int(4 * fs)
+    psd = oracle.psd_on_grid(oracle.welch_psd(strain_h.astype(np.float64), fs, L), fs, L, n)
+    st = oracle.strain_fft(strain_h, fs)
+    g = np.random.default_rng(5)
+    order = g.permutation(len(m1))
+    done, t_used, k = 0, 0.0, 0
+    while t_used < args.cpu_seconds and k < len(order):
+        take = order[k:k + 8]
+        k += len(take)
+        b = synth.taylorf2_bank(m1[take], m2[take], n, fs, f_low)
+        t0 = time.perf_counter()
+        oracle.filter_bank(st, psd, n, fs, f_low, b, np.arange(len(take)), 4.0)
+        t_used += time.perf_counter() - t0
+        done += len(take)
+    T = n / fs
+    return {"value": done * T / t_used, "unit": "template-s/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} fine templates x 1 detector x {T:.0f} s at {fs:.0f} Hz: FP64 matched filter "
+                      f"+ threshold (numpy FFT, one thread), {t_used:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2309_00019_amd import hs, search
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(json.dumps({"calib_copy_bytes": src.numel() * 4}))
+        return
+
+    fs, f_low = 2048.0, 20.0
+    n = int(args.seconds * fs)
+    T = n / fs
+    cfg = search.SearchConfig(fs=fs, f_low=f_low)
+    ctx = hs.Context(0)
+    dev = ctx.device
+    t_setup = time.perf_counter()
+
+    # ---- inputs -----------------------------------------------------------------------------
+    fm1, fm2 = synth.bank_by_tau0(args.fine, 1.4, 10.0, 1.0, 4.0, synth.rng(2, 0, 0, synth.BANK))
+    cm1, cm2 = synth.bank_by_tau0(args.coarse, 1.4, 10.0, 1.0, 4.0, synth.rng(2, 1, 0, synth.BANK))
+    inj = synth.injection_params(args.injections, synth.rng(2, 0, 0, synth.INJECT), 1.4, 10.0, 1.0, 4.0, T)
+    spacing = (T - 16.0) / max(1, args.injections)
+    inj["tc_h"] = 8.0 + spacing * (np.arange(args.injections) + 0.5)
+    dt =synth.rng(2, 1, 0, synth.INJECT).uniform(-0.010, 0.010, args.injections)
+    inj["tc_l"] = inj["tc_h"] + dt
+    strains = []
+    for det, key in ((0, "h"), (1, "l")):
+        injs = [dict(m1=inj["m1"][i], m2=inj["m2"][i], t_c=inj["tc_" + key][i], phi_c=inj["phi_" + key][i],
+                     snr=inj["snr_" + key][i]) for i in range(args.injections)]
+        s, _ = synth.make_strain(2, det, 0, n, fs, f_low, glitch_rate=0.05, injections=injs)
+        strains.append(s)
+    strain_h = torch.as_tensor(strains[0], device=dev)
+    strain_l = torch.as_tensor(strains[1], device=dev)
+    L = int(4 * fs)
+    psd_h = hs.hs_welch_psd(ctx, strain_h, fs, L)
+    psd_l = hs.hs_welch_psd(ctx, strain_l, fs, L)
+    log(f"[setup] generating and preparing {args.fine} fine + {args.coarse} coarse templates ({args.dtype})")
+    fine_h, fine_l = make_banks(ctx, hs, synth, n, fs, f_low, fm1, fm2, [psd_h, psd_l], args.dtype, args.chunk)
+    n1, fs1 = n // cfg.decim, fs / cfg.decim
+    coarse_h, coarse_l = make_banks(ctx, hs, synth, n1, fs1, f_low, cm1, cm2,
+                                    [psd_h[: n1 // 2 + 1].contiguous(), psd_l[: n1 // 2 + 1].contiguous()],
+                                    args.dtype, args.chunk)
+    torch.cuda.synchronize()
+    log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s")
+
+    def whiten_both():
+        ph = hs.hs_welch_psd(ctx, strain_h, fs, L)
+        pl = hs.hs_welch_psd(ctx, strain_l, fs, L)
+        sh = hs.hs_whiten(ctx, strain_h, fs, f_low, ph)
+        sl = hs.hs_whiten(ctx, strain_l, fs, f_low, pl)
+        return sh[None], sl[None]
+
+    def step_hier(timed=False):
+        sh, sl = whiten_both()
+        return search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg, time_mf=timed)
+
+    def step_flat(timed=False):
+        sh, sl = whiten_both()
+        return search.flat_search(ctx, sh, sl, fine_h, fine_l, cfg, time_mf=timed)
+
+    def timed(step, label):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = None
+        for i in range(args.steps):
+            res = step(timed=False)
+            log(f"[{label}] step {i + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        return wall, res
+
+    if args.only == "flat":
+        wall_f, res_f = timed(step_flat, "flat")
+        res_ft = step_flat(timed=True)
+        log(json.dumps({"flat_ms_per_step": wall_f * 1e3, "mf_ms": res_ft.mf_ms, "mf_calls": res_ft.mf_calls}))
+        ctx.close()
+        return
+    wall_h, res_h = timed(step_hier, "hier")
+    # a separate pass with per-call events around every matched-filter call
+    res_ht = step_hier(timed=True)
+    torch.cuda.synchronize()
+    out = {}
+    flat = None
+    if not args.no_flat and args.only == "both":
+        wall_f, res_f = timed(step_flat, "flat")
+        res_ft = step_flat(timed=True)
+        flat = dict(wall=wall_f, res=res_f, res_t=res_ft)
+
+    tick = cfg.ticks_per_second
+    inj_ticks = (inj["tc_h"] * tick).astype(np.int64)
+    found_h = found_injections(hs.as_records(res_h.coincs, hs.COINC), inj_ticks, int(0.1 * tick))
+    full_ts = 2 * args.fine * T                      # flat-equivalent template-seconds per step
+    value = full_ts / wall_h
+    raw_ts = res_h.template_seconds + res_h.stage1_template_seconds / cfg.decim
+
+    # roofline of the matched filter: one "launch" = mf_pass_a + mf_pass_b over one batch of
+    # templates; device time from events around every matched-filter call of the event-timed
+    # flat pass (the stage-2 calls of the hierarchical pass when the flat search is skipped)
+    src = flat["res_t"] if flat else res_ht
+    mf_b = mf_bytes(src.mf_units, hs)
+    launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel())) for n_, ids, _ in src.mf_units)
+    achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "matched filter: mf_pass_a + mf_pass_b over one template batch",
+            "per_launch_ms": round(src.mf_ms / max(1, launches), 4), "launches": launches,
+            "bytes_per_launch": int(mf_b / max(1, launches))}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "template-s/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_h * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f16": "f16-storage/f32"}[args.dtype],
+        "data": "synthetic",
+        "config": {"workload": "two-detector hierarchical search, 2 x %d s at 2048 Hz, coarse %d @ 512 Hz, "
+                               "fine %d @ 2048 Hz, glitches 0.05/s, %d injections, %d slides x 0.1 s, 15 ms"
+                               % (args.seconds, args.coarse, args.fine, args.injections, cfg.n_slides),
+                   "fine_templates": args.fine, "coarse_templates": args.coarse, "seconds": args.seconds,
+                   "value_definition": "flat-equivalent: fine templates x detectors x seconds / wall per step",
+                   "followed_templates": [int(c) for c in res_h.followed],
+                   "raw_template_seconds_per_s": round(raw_ts / wall_h, 1)},
+        "roofline": roof,
+        "injections": {"n": args.injections, "found_hier": int(found_h)},
+    }
+    if flat:
+        found_f = found_injections(hs.as_records(flat["res"].coincs, hs.COINC), inj_ticks, int(0.1 * tick))
+        out["flat"] = {"value": round(flat["res"].template_seconds / flat["wall"], 1),
+                       "ms_per_step": round(flat["wall"] * 1e3, 3)}
+        out["speedup_vs_flat"] = round(flat["wall"] / wall_h, 3)
+        out["injections"]["found_flat"] = int(found_f)
+        out["injections"]["extra_missed_fraction"] = round((found_f - found_h) / max(1, args.injections), 4)
+    if not args.no_cpu:
+        log("[cpu] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(args, synth, n, fs, f_low, strains[0], fm1, fm2)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,14 +68,38 @@ __global__ __launch_bounds__(256) void mf_pass_a(
         x[j] = v;
     }
     float2 *Yt = Y + (size_t)tb * 512 * (size_t)N1;
+    // Twiddles: W_512^{k2} = W_512^l W_32^j (W_32^j are compile-time constants); W_256^{l a} and
+    // the four-step W_N^{k1 m2} (m2 = 2(a + 16 b) + r) advance by short recurrences from table
+    // values, at most 15 products each (relative error ~1e-6, far below the SNR tolerance).
+    const float2 w512l = tw512[l];
+    const float2 w256l = tw512[2 * l];
+    const int ju = 32 * k1;  // < N
+    const float2 ustep = cmul(twhi[ju >> 10], twlo[ju & 1023]);  // W_N^{32 k1}
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         float2 v[16];
+        if (r) {
+            // cos(2 pi j / 32), j = 0..8
+            constexpr float C32[9] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f,
+                                      0.83146961230254523708f, 0.70710678118654752440f, 0.55557023301960222474f,
+                                      0.38268343236508977173f, 0.19509032201612826785f, 0.0f};
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = r ? cmul(x[j], tw512[l + 16 * j]) : x[j];
+            for (int j = 0; j < 16; ++j) {
+                const float cj = j <= 8 ? C32[j] : -C32[16 - j];
+                const float sj = j <= 8 ? C32[8 - j] : C32[j - 8];
+                v[j] = cmul(cmul(x[j], float2{cj, sj}), w512l);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = x[j];
+        }
         dft16<1>(v);  // v[a] = sum_j x[l + 16 j] W_16^{j a}
+        float2 wa = w256l;
 #pragma unroll
-        for (int a = 1; a < 16; ++a) v[a] = cmul(v[a], tw512[2 * l * a]);  // W_256^{l a}
+        for (int a = 1; a < 16; ++a) {  // W_256^{l a}
+            v[a] = cmul(v[a], wa);
+            wa = cmul(wa, w256l);
+        }
         if (r) __syncthreads();
 #pragma unroll
         for (int a = 0; a < 16; ++a) lds[l * PA_LDS_LSTRIDE + a * 16 + c] = v[a];
@@ -85,12 +109,13 @@ __global__ __launch_bounds__(256) void mf_pass_a(
 #pragma unroll
         for (int l2 = 0; l2 < 16; ++l2) w[l2] = lds[l2 * PA_LDS_LSTRIDE + a * 16 + c];
         dft16<1>(w);  // w[b] = 256-point output a + 16 b
+        const int j0 = k1 * (2 * a + r);  // < N
+        float2 tw = cmul(twhi[j0 >> 10], twlo[j0 & 1023]);
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
             const int m2 = 2 * (a + 16 * b) + r;
-            const int jj = k1 * m2;  // < N
-            const float2 tw = cmul(twhi[jj >> 10], twlo[jj & 1023]);
             Yt[(size_t)m2 * N1 + k1] = cmul(w[b], tw);
+            tw = cmul(tw, ustep);
         }
     }
 }
@@ -114,10 +139,16 @@ __device__ __forceinline__ int pass_out_index(int ln, int e) {
     return (j / Ns) * Ns * R + (j % Ns) + r * Ns;
 }
 
+// LDS rows hold one pad slot after every 16 elements: the first pass writes 16 consecutive
+// elements per lane (a 128-byte lane stride), which without the pad puts every lane of a
+// wavefront on the same LDS banks; with it the lane stride is 136 bytes and the accesses of
+// 16 (32-bank) or 32 (64-bank) consecutive lanes fall on distinct banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
 template <int N1, int LPR, int R, int Ns>
 __device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int ln) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[pass_out_index<LPR, R, Ns>(ln, e)] = v[e];
+    for (int e = 0; e < 16; ++e) row[lds_pad(pass_out_index<LPR, R, Ns>(ln, e))] = v[e];
 }
 
 template <int N1, int LPR, int R, int Ns>
@@ -128,7 +159,7 @@ __device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int 
         const int k = j % Ns;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float2 x = row[j + r * (N1 / R)];
+            float2 x = row[lds_pad(j + r * (N1 / R))];
             if (r > 0) x = cmul(x, tw[k * r * (N1 / (Ns * R))]);
             v[b * R + r] = x;
         }
@@ -146,8 +177,13 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
     constexpr int LPR = N1 / 16;    // lanes per row
     constexpr int RPB = 256 / LPR;  // rows per block
     constexpr int R2 = PassBPlan<N1>::R2, R3 = PassBPlan<N1>::R3;
-    __shared__ float2 lds[N1 > 16 ? RPB * N1 : 1];
+    constexpr int ROW = N1 + N1 / 16;  // padded row length
+    constexpr int LDS_N = N1 > 16 ? RPB * ROW : 1024;
+    __shared__ float2 lds[LDS_N];
+    __shared__ unsigned int s_count;
+    __shared__ unsigned long long s_base;
     if (*bad) return;
+    if (threadIdx.x == 0) s_count = 0;
     const int tb = blockIdx.y;
     const int lr = threadIdx.x / LPR;
     const int ln = threadIdx.x % LPR;
@@ -158,7 +194,7 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = src[ln + r * LPR];
     dft16<1>(v);
-    float2 *row = lds + (N1 > 16 ? lr * N1 : 0);
+    float2 *row = lds + (N1 > 16 ? lr * ROW : 0);
     if constexpr (R2 > 1) {
         lds_write_pass<N1, LPR, 16, 1>(row, v, ln);
         __syncthreads();
@@ -184,8 +220,16 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
             zt[m2 + 512 * m1] = float2{v[e].x * zs, v[e].y * zs};
         }
     } else {
+        // Candidates are staged in LDS (the transform buffer, free after the last pass): each
+        // wavefront reserves slots with one LDS atomic per ballot, then the workgroup reserves
+        // its block of the global list with a single atomic and writes it out contiguously.
+        // Slots beyond the staging capacity (only near very loud signals) go straight to the
+        // global list, one atomic per lane.
+        constexpr int STAGE = LDS_N / 2;  // hs_candidate = 2 float2
+        hs_candidate *stage = reinterpret_cast<hs_candidate *>(lds);
         const int lane = __lane_id();
         const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        __syncthreads();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const float2 z = v[e];
@@ -194,22 +238,33 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
             const unsigned long long mask = __ballot(p);
             if (mask) {
                 const int leader = __ffsll((long long)mask) - 1;
-                unsigned long long b0 = 0;
-                if (lane == leader) b0 = atomicAdd(counter, (unsigned long long)__popcll(mask));
+                unsigned int b0 = 0;
+                if (lane == leader) b0 = atomicAdd(&s_count, (unsigned int)__popcll(mask));
                 b0 = __shfl(b0, leader);
                 if (p) {
-                    const unsigned long long idx = b0 + (unsigned long long)__popcll(mask & below);
-                    if (idx < (unsigned long long)cap) {
-                        const int m1 = pass_out_index<LPR, RL, NsL>(ln, e);
-                        hs_candidate o;
-                        o.tpos = id0 + tb;
-                        o.m = m2 + 512 * m1;
-                        o.rho2 = r2;
-                        o.phase = atan2f(z.y, z.x);
-                        cand[idx] = o;
+                    const unsigned int slot = b0 + (unsigned int)__popcll(mask & below);
+                    const int m1 = pass_out_index<LPR, RL, NsL>(ln, e);
+                    hs_candidate o;
+                    o.tpos = id0 + tb;
+                    o.m = m2 + 512 * m1;
+                    o.rho2 = r2;
+                    o.phase = atan2f(z.y, z.x);
+                    if (slot < (unsigned int)STAGE) {
+                        stage[slot] = o;
+                    } else {
+                        const unsigned long long idx = atomicAdd(counter, 1ull);
+                        if (idx < (unsigned long long)cap) cand[idx] = o;
                     }
                 }
             }
+        }
+        __syncthreads();
+        const unsigned int k = s_count < (unsigned int)STAGE ? s_count : (unsigned int)STAGE;
+        if (threadIdx.x == 0) s_base = k ? atomicAdd(counter, (unsigned long long)k) : 0ull;
+        __syncthreads();
+        for (unsigned int i = threadIdx.x; i < k; i += 256) {
+            const unsigned long long idx = s_base + i;
+            if (idx < (unsigned long long)cap) cand[idx] = stage[i];
         }
     }
 }

@@ -157,6 +157,13 @@ class PreparedBank:
                             torch.empty(T, dtype=torch.float64, device=device))
 
 
+def mf_batch_templates(n: int, n_ids: int) -> int:
+    """Templates per pass-A/pass-B launch in hs_matched_filter (same rule as the library)."""
+    mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
+    budget = (mb << 20) if mb > 0 else (256 << 20)
+    return max(1, min(65535, n_ids, budget // (n * 8)))
+
+
 def hs_abi_version() -> int:
     return load_library().hs_abi_version()
 

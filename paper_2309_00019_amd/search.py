@@ -1,0 +1,161 @@
+"""Flat and two-stage hierarchical searches composed from the libhs entry points.
+
+Control flow only: every numerical step is one of the C-ABI calls in ``hs``.
+
+Flat (Sec. II): each segment of each detector is whitened, filtered with the full fine bank
+at the full rate (threshold 4), clustered into triggers; two-detector coincidence over K
+slides gives the foreground and the background counts of Eq. (6).
+
+Hierarchical (Sec. III): stage 1 filters the leading quarter of the same whitened spectrum
+(ideal decimation to fs/4, same df) with the coarse bank at threshold 3.5, coincides over
+zero lag plus N_sh1 long slides, follows every coincidence with network SNR >= rho1 into the
+union of fine-bank chirp-mass neighbourhoods of its segments, filters those templates at the
+full rate (threshold 4) and coincides over the K background slides.
+
+Time is int64 ticks of 1/ticks_per_second s; sample m of segment s has tick
+s * seg_ticks + m * ticks_per_sample.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import hs
+
+
+@dataclass
+class SearchConfig:
+    fs: float = 2048.0
+    f_low: float = 20.0
+    decim: int = 4                # stage-1 rate = fs / decim
+    thr1: float = 3.5
+    thr2: float = 4.0
+    window_sec: float = 1.0       # trigger clustering window
+    ticks_per_second: int = 51200
+    n_sh1: int = 16               # stage-1 slides (reading of Sec. III, scaled to the data length)
+    t_sh1_sec: float = 15.0
+    rho1: float = 7.0             # stage-1 follow-up threshold on the network SNR
+    mc_frac: float = 0.05         # neighbourhood: |Mc_f - Mc_c| <= frac Mc_c
+    n_slides: int = 2000          # stage-2 / flat background slides
+    step_sec: float = 0.1
+    coinc_window_sec: float = 0.015
+    cluster_sec: float = 1.0      # per-slide coincidence clustering window
+    edges: tuple = (6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0, 14.0, 16.0, 20.0)
+
+
+@dataclass
+class SearchResult:
+    trig_h: torch.Tensor
+    trig_l: torch.Tensor
+    coincs: torch.Tensor
+    bg_counts: np.ndarray
+    t_b: float
+    templates_filtered: int              # (template, segment, detector) applications at full rate
+    template_seconds: float              # full-rate template-seconds filtered
+    stage1_template_seconds: float = 0.0
+    stage1_coincs: torch.Tensor = None
+    followed: list = field(default_factory=list)
+    mf_ms: float = 0.0                   # device time inside matched-filter calls (events)
+    mf_calls: int = 0
+    mf_units: list = field(default_factory=list)   # (n, ids, bank) per matched-filter call
+
+
+class _MFTimer:
+    """Accumulates device time of matched-filter calls with events on the library's stream."""
+
+    def __init__(self, ctx, enabled):
+        self.ctx, self.enabled, self.ms, self.calls, self.units = ctx, enabled, 0.0, 0, []
+
+    def run(self, fn, n, ids, bank):
+        if not self.enabled:
+            return fn()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(self.ctx.stream)
+        out = fn()
+        e.record(self.ctx.stream)
+        e.synchronize()
+        self.ms += s.elapsed_time(e)
+        self.calls += 1
+        self.units.append((n, ids, bank))
+        return out
+
+
+def whiten_all(ctx, strains, psds, cfg: SearchConfig):
+    """Whitened spectra [n_seg, n/2] for one detector (strains [n_seg, n] float32 device)."""
+    n_seg, n = strains.shape
+    out = torch.empty((n_seg, n // 2), dtype=torch.complex64, device=strains.device)
+    for s in range(n_seg):
+        hs.hs_whiten(ctx, strains[s], cfg.fs, cfg.f_low, psds[s], out=out[s])
+    return out
+
+
+def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None):
+    """Filter + cluster every segment of one detector; returns concatenated trigger records."""
+    tps = int(round(cfg.ticks_per_second / fs))
+    seg_ticks = specs.shape[1] * 2 * int(round(cfg.ticks_per_second / cfg.fs))
+    window = int(round(cfg.window_sec * fs))
+    parts = []
+    for s in range(specs.shape[0]):
+        ids = ids_per_seg[s]
+        if ids.numel() == 0:
+            continue
+        f = lambda: hs.hs_matched_filter(ctx, specs[s], n, fs, bank, ids, thr)
+        cand = timer.run(f, n, ids, bank) if timer else f()
+        parts.append(hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks,
+                                            ticks_per_sample=tps))
+    if not parts:
+        return torch.zeros((0, 6), dtype=torch.int32, device=specs.device)
+    return torch.cat(parts) if len(parts) > 1 else parts[0]
+
+
+def _coinc(ctx, th, tl, n_tmpl, n_slides, step_sec, cfg, wrap, edges):
+    tk = cfg.ticks_per_second
+    return hs.hs_timeslide_coinc(ctx, th, tl, n_tmpl, n_slides, int(round(step_sec * tk)),
+                                 int(round(cfg.coinc_window_sec * tk)), wrap, int(round(cfg.cluster_sec * tk)),
+                                 edges)
+
+
+def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=False) -> SearchResult:
+    """Flat search; fine_h / fine_l are the fine bank prepared with each detector's PSD."""
+    n = spec_h.shape[1] * 2
+    n_seg = spec_h.shape[0]
+    fine = fine_h
+    all_ids = torch.arange(fine.n_tmpl, dtype=torch.int32, device=spec_h.device)
+    timer = _MFTimer(ctx, time_mf)
+    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, [all_ids] * n_seg, cfg.thr2, cfg, timer)
+    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, [all_ids] * n_seg, cfg.thr2, cfg, timer)
+    wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
+    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
+    T = n / cfg.fs
+    apps = 2 * n_seg * fine.n_tmpl
+    return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
+                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units)
+
+
+def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l, cfg: SearchConfig,
+                        time_mf=False) -> SearchResult:
+    """Two-stage search; each bank is given per detector (prepared with that detector's PSD)."""
+    coarse, fine = coarse_h, fine_h
+    n = spec_h.shape[1] * 2
+    n_seg = spec_h.shape[0]
+    n1, fs1 = n // cfg.decim, cfg.fs / cfg.decim
+    dev = spec_h.device
+    timer = _MFTimer(ctx, time_mf)
+    c_ids = torch.arange(coarse.n_tmpl, dtype=torch.int32, device=dev)
+    t1h = detector_triggers(ctx, spec_h, n1, fs1, coarse_h, [c_ids] * n_seg, cfg.thr1, cfg, timer)
+    t1l = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer)
+    tpt = int(round(cfg.ticks_per_second / cfg.fs))
+    seg_ticks = n * tpt
+    wrap = n_seg * seg_ticks
+    c1, _ = _coinc(ctx, t1h, t1l, coarse.n_tmpl, cfg.n_sh1, cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32))
+    ids2, counts = hs.hs_followup(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, cfg.mc_frac, seg_ticks, n_seg)
+    per_seg = [ids2[s, :counts[s]] for s in range(n_seg)]
+    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, per_seg, cfg.thr2, cfg, timer)
+    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, per_seg, cfg.thr2, cfg, timer)
+    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
+    T = n / cfg.fs
+    apps = 2 * int(sum(counts))
+    return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
+                        stage1_template_seconds=2 * n_seg * coarse.n_tmpl * T, stage1_coincs=c1, followed=counts,
+                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units)
