@@ -28,6 +28,20 @@
 namespace hs {
 
 static constexpr int PA_LDS_LSTRIDE = 16 * 16 + 16;  // float2 per l-block (padded by 16)
+static constexpr int PB_THREADS = 128;                // pass-B workgroup size
+static constexpr int MF_STRIPES = 64;                 // candidate lists (power of two)
+
+// Concatenates the striped candidate lists into the caller's buffer (in stripe order).
+__global__ __launch_bounds__(256) void mf_compact(const hs_candidate *__restrict__ buf,
+                                                  const unsigned long long *__restrict__ count, int64_t stripe_cap,
+                                                  hs_candidate *__restrict__ out, int64_t cap) {
+    const int s = blockIdx.y;
+    unsigned long long off = 0;
+    for (int q = 0; q < s; ++q) off += count[q] < (unsigned long long)stripe_cap ? count[q] : stripe_cap;
+    const unsigned long long n = count[s] < (unsigned long long)stripe_cap ? count[s] : stripe_cap;
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull)
+        if (off + i < (unsigned long long)cap) out[off + i] = buf[(size_t)s * stripe_cap + i];
+}
 
 __global__ void mf_validate(const int32_t *__restrict__ ids, int32_t n_ids, int32_t n_tmpl,
                             const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
@@ -42,8 +56,9 @@ __global__ void mf_validate(const int32_t *__restrict__ ids, int32_t n_ids, int3
     if (klo[t] < 1 || klo[t] < k0[t] || khi[t] > half - 1) atomicOr(bad, 2);
 }
 
+// 256 threads, at least 4 waves per SIMD (caps VGPRs at 128 so 4 workgroups fit a CU).
 template <typename ST>
-__global__ __launch_bounds__(256) void mf_pass_a(
+__global__ __launch_bounds__(256, 4) void mf_pass_a(
     const float2 *__restrict__ dspec, const typename ST::elem *__restrict__ spectra,
     const int64_t *__restrict__ offset, const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
     const int32_t *__restrict__ khi, const int32_t *__restrict__ ids, int32_t id0, int32_t N1,
@@ -68,9 +83,11 @@ __global__ __launch_bounds__(256) void mf_pass_a(
         x[j] = v;
     }
     float2 *Yt = Y + (size_t)tb * 512 * (size_t)N1;
-    // Twiddles: W_512^{k2} = W_512^l W_32^j (W_32^j are compile-time constants); W_256^{l a} and
-    // the four-step W_N^{k1 m2} (m2 = 2(a + 16 b) + r) advance by short recurrences from table
-    // values, at most 15 products each (relative error ~1e-6, far below the SNR tolerance).
+    // Twiddles: W_512^{k2} = W_512^l W_32^j; the W_32^j are compile-time constants applied
+    // before the radix-16 DFT over j, and the common factor W_512^l is merged after it with
+    // W_256^{l a}.  W_256^{l a} and the four-step W_N^{k1 m2} (m2 = 2(a + 16 b) + r) advance by
+    // short recurrences from table values, at most 15 products each (relative error ~1e-6,
+    // far below the SNR tolerance).
     const float2 w512l = tw512[l];
     const float2 w256l = tw512[2 * l];
     const int ju = 32 * k1;  // < N
@@ -83,22 +100,34 @@ __global__ __launch_bounds__(256) void mf_pass_a(
             constexpr float C32[9] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f,
                                       0.83146961230254523708f, 0.70710678118654752440f, 0.55557023301960222474f,
                                       0.38268343236508977173f, 0.19509032201612826785f, 0.0f};
+            v[0] = x[0];
+            v[8] = float2{-x[8].y, x[8].x};  // x W_32^8 = i x
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 1; j < 16; ++j) {
+                if (j == 8) continue;
                 const float cj = j <= 8 ? C32[j] : -C32[16 - j];
                 const float sj = j <= 8 ? C32[8 - j] : C32[j - 8];
-                v[j] = cmul(cmul(x[j], float2{cj, sj}), w512l);
+                v[j] = cmul(x[j], float2{cj, sj});
             }
         } else {
 #pragma unroll
             for (int j = 0; j < 16; ++j) v[j] = x[j];
         }
-        dft16<1>(v);  // v[a] = sum_j x[l + 16 j] W_16^{j a}
-        float2 wa = w256l;
+        dft16<1>(v);  // v[a] = sum_j x[l + 16 j] W_32^{r j} W_16^{j a}
+        if (r) {
+            float2 wa = w512l;  // W_512^l W_256^{l a}
 #pragma unroll
-        for (int a = 1; a < 16; ++a) {  // W_256^{l a}
-            v[a] = cmul(v[a], wa);
-            wa = cmul(wa, w256l);
+            for (int a = 0; a < 16; ++a) {
+                v[a] = cmul(v[a], wa);
+                wa = cmul(wa, w256l);
+            }
+        } else {
+            float2 wa = w256l;  // W_256^{l a}
+#pragma unroll
+            for (int a = 1; a < 16; ++a) {
+                v[a] = cmul(v[a], wa);
+                wa = cmul(wa, w256l);
+            }
         }
         if (r) __syncthreads();
 #pragma unroll
@@ -139,16 +168,23 @@ __device__ __forceinline__ int pass_out_index(int ln, int e) {
     return (j / Ns) * Ns * R + (j % Ns) + r * Ns;
 }
 
-// LDS rows hold one pad slot after every 16 elements: the first pass writes 16 consecutive
-// elements per lane (a 128-byte lane stride), which without the pad puts every lane of a
-// wavefront on the same LDS banks; with it the lane stride is 136 bytes and the accesses of
-// 16 (32-bank) or 32 (64-bank) consecutive lanes fall on distinct banks.
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+// Placement of row element i in LDS.  The first pass writes 16 consecutive elements per lane
+// (a 128-byte lane stride), which unmapped puts the lanes of a wavefront on the same banks.
+// The LDS serves 8-byte accesses 32 lanes per cycle over 64 four-byte banks, so an access is
+// conflict-free when its 32 lanes hit distinct (element mod 32) slots.  Rows of >= 512
+// elements use an XOR swizzle of the low five bits (no padding) and shorter rows one pad
+// element per 16; both were checked conflict-free for every pass of every plan with a model
+// of that bank mapping.
+template <int N1> __device__ __forceinline__ int lds_map(int i) {
+    if constexpr (N1 >= 512) return i ^ (((i >> 5) ^ ((i >> 8) << 4)) & 31);
+    else return i + (i >> 4);
+}
+template <int N1> constexpr int lds_row_len() { return N1 >= 512 ? N1 : N1 + N1 / 16; }
 
 template <int N1, int LPR, int R, int Ns>
 __device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int ln) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[lds_pad(pass_out_index<LPR, R, Ns>(ln, e))] = v[e];
+    for (int e = 0; e < 16; ++e) row[lds_map<N1>(pass_out_index<LPR, R, Ns>(ln, e))] = v[e];
 }
 
 template <int N1, int LPR, int R, int Ns>
@@ -159,7 +195,7 @@ __device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int 
         const int k = j % Ns;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float2 x = row[lds_pad(j + r * (N1 / R))];
+            float2 x = row[lds_map<N1>(j + r * (N1 / R))];
             if (r > 0) x = cmul(x, tw[k * r * (N1 / (Ns * R))]);
             v[b * R + r] = x;
         }
@@ -168,16 +204,16 @@ __device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int 
 }
 
 template <int N1, bool WRITE_Z>
-__global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
+__global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
                                                  const int32_t *__restrict__ ids, int32_t id0, float thr2,
                                                  const float2 *__restrict__ twN1, const int32_t *__restrict__ bad,
                                                  hs_candidate *__restrict__ cand,
                                                  unsigned long long *__restrict__ counter, int64_t cap,
                                                  float2 *__restrict__ zout) {
     constexpr int LPR = N1 / 16;    // lanes per row
-    constexpr int RPB = 256 / LPR;  // rows per block
+    constexpr int RPB = PB_THREADS / LPR;  // rows per block
     constexpr int R2 = PassBPlan<N1>::R2, R3 = PassBPlan<N1>::R3;
-    constexpr int ROW = N1 + N1 / 16;  // padded row length
+    constexpr int ROW = lds_row_len<N1>();
     constexpr int LDS_N = N1 > 16 ? RPB * ROW : 1024;
     __shared__ float2 lds[LDS_N];
     __shared__ unsigned int s_count;
@@ -222,11 +258,15 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
     } else {
         // Candidates are staged in LDS (the transform buffer, free after the last pass): each
         // wavefront reserves slots with one LDS atomic per ballot, then the workgroup reserves
-        // its block of the global list with a single atomic and writes it out contiguously.
-        // Slots beyond the staging capacity (only near very loud signals) go straight to the
-        // global list, one atomic per lane.
+        // its block of one of MF_STRIPES candidate lists with a single atomic and writes it out
+        // contiguously (striping keeps same-address atomics from serialising across the GPU;
+        // the lists are concatenated after the last batch).  Slots beyond the staging capacity
+        // (only near very loud signals) go straight to the list, one atomic per lane.
         constexpr int STAGE = LDS_N / 2;  // hs_candidate = 2 float2
         hs_candidate *stage = reinterpret_cast<hs_candidate *>(lds);
+        const unsigned int stripe = (blockIdx.y * gridDim.x + blockIdx.x) & (MF_STRIPES - 1);
+        counter += stripe;
+        cand += (size_t)stripe * (size_t)cap;
         const int lane = __lane_id();
         const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         __syncthreads();
@@ -262,7 +302,7 @@ __global__ __launch_bounds__(256) void mf_pass_b(const float2 *__restrict__ Y, c
         const unsigned int k = s_count < (unsigned int)STAGE ? s_count : (unsigned int)STAGE;
         if (threadIdx.x == 0) s_base = k ? atomicAdd(counter, (unsigned long long)k) : 0ull;
         __syncthreads();
-        for (unsigned int i = threadIdx.x; i < k; i += 256) {
+        for (unsigned int i = threadIdx.x; i < k; i += PB_THREADS) {
             const unsigned long long idx = s_base + i;
             if (idx < (unsigned long long)cap) cand[idx] = stage[i];
         }
@@ -275,7 +315,7 @@ static int launch_pass_b(hs_ctx *ctx, int N1, dim3 grid, const float2 *Y, const 
                          unsigned long long *counter, int64_t cap, float2 *zout) {
 #define HS_PB(NN)                                                                                         \
     case NN:                                                                                              \
-        hipLaunchKernelGGL((mf_pass_b<NN, WRITE_Z>), grid, dim3(256), 0, ctx->stream, Y, r2s, ids, id0, thr2, \
+        hipLaunchKernelGGL((mf_pass_b<NN, WRITE_Z>), grid, dim3(PB_THREADS), 0, ctx->stream, Y, r2s, ids, id0, thr2, \
                            twN1, bad, cand, counter, cap, zout);                                          \
         break;
     switch (N1) {
@@ -321,15 +361,20 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
     HS_TRY(twiddles_f32(ctx, ilog2(N1), &twN1));
 
+    // Striped candidate lists: MF_STRIPES lists of stripe_cap records each (the caller's
+    // capacity spread over the stripes, plus slack for uneven filling).
+    const int64_t stripe_cap = WRITE_Z ? 1 : cap / MF_STRIPES + 4096;
     float2 *Y;
     unsigned long long *counter;
+    hs_candidate *sbuf;
     int32_t *bad;
     Carver cv;
     cv.add(&Y, (size_t)tb_max * n);
-    cv.add(&counter, 1);
+    cv.add(&counter, MF_STRIPES);
+    cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap);
     cv.add(&bad, 1);
     HS_TRY(cv.commit(ctx));
-    HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), 1, 0));
+    HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), MF_STRIPES, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
     hipLaunchKernelGGL(mf_validate, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
                        bank->n_tmpl, bank->k0, bank->k_lo, bank->k_hi, n / 2, bad);
@@ -358,23 +403,37 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
             break;
         }
         HS_HIP(hipGetLastError());
-        const dim3 gb((unsigned)(N1 / 8), (unsigned)tb);
-        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, gb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, cand,
-                                      counter, cap, zout));
+        const dim3 gb((unsigned)(512 * N1 / (16 * PB_THREADS)), (unsigned)tb);  // 512 rows / rows per block
+        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, gb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, sbuf,
+                                      counter, stripe_cap, zout));
     }
-    struct {
-        unsigned long long count;
-        int32_t bad;
-    } h{};
-    HS_TRY(read_back(ctx, counter, &h.count, sizeof(h.count)));
-    HS_TRY(read_back(ctx, bad, &h.bad, sizeof(h.bad)));
-    HS_REQUIRE(h.bad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
-               h.bad);
+    if (!WRITE_Z && cap > 0) {
+        hipLaunchKernelGGL(mf_compact, dim3(16, MF_STRIPES), dim3(256), 0, ctx->stream, sbuf, counter, stripe_cap,
+                           cand, cap);
+        HS_HIP(hipGetLastError());
+    }
+    unsigned long long hc[MF_STRIPES];
+    int32_t hbad = 0;
+    HS_TRY(read_back(ctx, counter, hc, sizeof(hc)));
+    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_REQUIRE(hbad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
+               hbad);
     if (!WRITE_Z) {
-        *n_cand = (int64_t)h.count;
-        if ((int64_t)h.count > cap)
-            return set_error(HS_EOVERFLOW, "matched filter: %llu candidates exceed capacity %lld", h.count,
+        unsigned long long total = 0, most = 0;
+        for (int s = 0; s < MF_STRIPES; ++s) {
+            total += hc[s];
+            most = hc[s] > most ? hc[s] : most;
+        }
+        *n_cand = (int64_t)total;
+        if ((int64_t)total > cap)
+            return set_error(HS_EOVERFLOW, "matched filter: %llu candidates exceed capacity %lld", total,
                              (long long)cap);
+        if ((int64_t)most > stripe_cap) {
+            // one list filled up although the total fits: ask for room that fits the fullest list
+            *n_cand = (int64_t)(most * MF_STRIPES);
+            return set_error(HS_EOVERFLOW, "matched filter: candidate list %llu > %lld; retry with capacity %lld",
+                             most, (long long)stripe_cap, (long long)*n_cand);
+        }
     }
     return HS_OK;
 }
