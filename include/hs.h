@@ -14,6 +14,7 @@
  *   hs_matched_filter   complex SNR series of Eq. (1)/(2), threshold (Sec. II)
  *   hs_snr_series       the same SNR series written out in full (diagnostics)
  *   hs_cluster_triggers peak clustering of above-threshold samples into triggers
+ *   hs_chisq            power-consistency chi-square and re-weighted SNR (Eq. (4))
  *   hs_timeslide_coinc  two-detector coincidence over time slides, per-slide
  *                       clustering, background counts for Eq. (6) (Secs. I-II)
  *   hs_followup         stage-1 selection and union of fine-bank neighbourhoods
@@ -90,6 +91,8 @@ typedef struct {
     const int32_t *k_hi;      /* [n_tmpl] last band bin (inclusive) */
     const void *spectra;
     const float *rho2_scale;  /* [n_tmpl] factor applied to |z|^2 (undoes storage scaling) */
+    int32_t chisq_bins;       /* p of the power-consistency test (0 = no edges) */
+    const int32_t *chisq_edges; /* [n_tmpl][p + 1] bin edges (NULL when chisq_bins == 0) */
 } hs_bank;
 
 /* Context: binds a device and a HIP stream (hipStream_t; NULL = default stream). */
@@ -138,16 +141,22 @@ int hs_whiten(hs_ctx *ctx, const float *strain, int64_t n, double fs, double f_l
  * element near 2^14 for HS_BF16/HS_F16; rho2_scale_out[t] = 1/scale_t^2.
  * With this, sum_k d~_k conj(w~_k) e^{2 pi i k m / n} / scale_t is the complex
  * SNR z[m] of Eq. (1)/(2) (quadrature form of Appendix A).
+ * With chisq_bins = p >= 2 it also writes the edges of the p contiguous bins of
+ * equal template power |h~_k|^2 / S_k used by hs_chisq (the power-consistency
+ * test Sec. II cites): chisq_edges_out[t][0] = k_lo, [t][p] = k_hi + 1, and
+ * edge l (0 < l < p) = the first bin whose cumulative power from k_lo reaches
+ * l/p of the template's total (float64 sums).
  *   psd device double [n/2 + 1]; raw, offset, k0, kstart, k1 device;
  *   spectra_out device (element size 8 for F32, 4 otherwise);
- *   k_lo_out, k_hi_out, rho2_scale_out, sigma_out device [n_tmpl].
- * HS_EINVAL if a band is empty or k1 >= k0 is violated.
+ *   k_lo_out, k_hi_out, rho2_scale_out, sigma_out device [n_tmpl];
+ *   chisq_edges_out device int32 [n_tmpl][p + 1] (NULL when chisq_bins == 0).
+ * HS_EINVAL if a band is empty or k1 >= k0 is violated, or chisq_bins is 1 or > 16.
  */
 int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, const double *psd,
                     int32_t n_tmpl, const void *raw, const int64_t *offset, const int32_t *k0,
                     const int32_t *kstart, const int32_t *k1, int32_t dtype, void *spectra_out,
                     int32_t *k_lo_out, int32_t *k_hi_out, float *rho2_scale_out,
-                    double *sigma_out);
+                    double *sigma_out, int32_t chisq_bins, int32_t *chisq_edges_out);
 
 /*
  * Matched filter + threshold (Sec. II: a sample is kept when rho >= thr,
@@ -185,6 +194,25 @@ int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, i
                         const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int32_t seg,
                         int64_t seg_t0, int64_t ticks_per_sample, hs_trigger *out, int64_t cap,
                         int64_t *n_out);
+
+/*
+ * Power-consistency chi-square and re-weighted SNR of Sec. II, Eq. (4).  For every
+ * trigger with snr >= rho_min (others are copied unchanged with chi2_r = 0), at
+ * its sample m = (tick - seg_t0) / ticks_per_sample of this segment:
+ *   z_l = sum_{k in bin l} spec[k] conj(w~[k]) e^{2 pi i k m / n} / scale   (p bins)
+ *   chi2 = p sum_l |z_l - z/p|^2,  z = sum_l z_l,  chi2_r = chi2 / (2p - 2)
+ *   rho~ = snr / [(1 + chi2_r^3)/2]^(1/6) if chi2_r >= 1, else snr     (Eq. (4))
+ * Bin sums accumulate in float64.  trig_out receives the triggers with snr
+ * replaced by rho~ (the statistic hs_timeslide_coinc then combines).
+ *   spec, bank as for hs_matched_filter (bank prepared with chisq_bins >= 2);
+ *   trig device hs_trigger [n_trig] of this segment (tmpl in [0, n_tmpl));
+ *   chisq_out device float [n_trig]; trig_out device hs_trigger [n_trig]
+ *   (may alias trig).
+ * HS_EINVAL if a trigger's tmpl or tick does not belong to this bank/segment.
+ */
+int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+             const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
+             float rho_min, float *chisq_out, hs_trigger *trig_out);
 
 /*
  * Two-detector coincidence over time slides (Sec. I; Sec. II, Eq. (6)).

@@ -37,3 +37,6 @@ __all__ = [
     "timeslide_coinc", "false_alarm_rate", "coinc_stat", "followup_templates",
     "flat_search", "hierarchical_search", "speedup_eq8",
 ]
+from .chisq import chisq_bin_edges, chisq_at, reweighted_snr  # noqa: E402
+
+__all__ += ["chisq_bin_edges", "chisq_at", "reweighted_snr"]

@@ -22,6 +22,8 @@ from .spectral import strain_fft
 from .filter import filter_bank, triggers_from_candidates
 from .coinc import timeslide_coinc
 from .followup import followup_templates
+from .filter import band_edges, template_sigma
+from .chisq import chisq_bin_edges, chisq_at, reweighted_snr
 
 
 def _concat(parts):
@@ -29,9 +31,31 @@ def _concat(parts):
     return {k: np.concatenate([p[k] for p in parts]) for k in keys}
 
 
+def reweight_triggers(tr, st, psd, n, fs, f_low, bank, chisq_bins: int, rho_min: float, tps: int, seg_t0: int):
+    """Eq. (4) on one segment's triggers: snr -> rho~ for triggers with snr >= rho_min
+    (chi-square per ``chisq``); adds columns snr_raw and chisq."""
+    snr = np.asarray(tr["snr"], np.float64)
+    chi = np.zeros(len(snr))
+    for i in np.nonzero(snr >= rho_min)[0]:
+        t = int(tr["tmpl"][i])
+        h = bank.spectrum(t)
+        k_lo, k_hi = band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        sig = template_sigma(h, psd, n, fs, k_lo, k_hi)
+        e = chisq_bin_edges(h, psd, k_lo, k_hi, chisq_bins)
+        m = (int(tr["tick"][i]) - seg_t0) // tps
+        chi[i] = chisq_at(st, h, psd, n, fs, sig, m, e)[0]
+    out = dict(tr)
+    out["snr_raw"] = snr
+    out["chisq"] = chi
+    out["snr"] = reweighted_snr(snr, chi)
+    return out
+
+
 def detector_triggers(segments, psds, fs: float, f_low: float, bank, tmpl_ids_per_seg, thr: float,
-                      window_sec: float, ticks_per_second: int, decim: int = 1):
-    """Triggers of one detector over all segments.  ``decim`` > 1 filters at fs/decim."""
+                      window_sec: float, ticks_per_second: int, decim: int = 1, chisq_bins: int = 8,
+                      chisq_rho_min: float = None):
+    """Triggers of one detector over all segments.  ``decim`` > 1 filters at fs/decim.
+    With ``chisq_rho_min`` set, snr is the re-weighted SNR of Eq. (4)."""
     out = []
     for s, seg in enumerate(segments):
         n_full = len(seg)
@@ -45,16 +69,20 @@ def detector_triggers(segments, psds, fs: float, f_low: float, bank, tmpl_ids_pe
         seg_ticks = n_full * int(round(ticks_per_second / fs))
         tr = triggers_from_candidates(c["tpos"], c["m"], c["rho2"], c["phase"], ids,
                                       int(round(window_sec * f)), s, s * seg_ticks, tps)
+        if chisq_rho_min is not None:
+            tr = reweight_triggers(tr, st, psd, n, f, f_low, bank, chisq_bins, chisq_rho_min, tps, s * seg_ticks)
         out.append(tr)
     return _concat(out)
 
 
 def flat_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, bank, thr=4.0, window_sec=1.0,
                 ticks_per_second=51200, n_slides=2000, step_sec=0.1, coinc_window_sec=0.015,
-                cluster_sec=1.0, edges=(8.0,)):
+                cluster_sec=1.0, edges=(8.0,), chisq_bins=8, chisq_rho_min=None):
     ids = [np.arange(bank.n_tmpl)] * len(h_segments)
-    th = detector_triggers(h_segments, h_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second)
-    tl = detector_triggers(l_segments, l_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second)
+    th = detector_triggers(h_segments, h_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second,
+                           chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
+    tl = detector_triggers(l_segments, l_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second,
+                           chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
     wrap = len(h_segments) * len(h_segments[0]) * int(round(ticks_per_second / fs))
     co = timeslide_coinc(th, tl, n_slides, int(round(step_sec * ticks_per_second)),
                          int(round(coinc_window_sec * ticks_per_second)), wrap,
@@ -67,7 +95,7 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                         decim=4, thr1=3.5, thr2=4.0, window_sec=1.0, ticks_per_second=51200,
                         n_sh1=16, t_sh1_sec=15.0, rho1=7.0, mc_frac=0.05,
                         n_slides=2000, step_sec=0.1, coinc_window_sec=0.015, cluster_sec=1.0,
-                        edges=(8.0,)):
+                        edges=(8.0,), chisq_bins=8, chisq_rho_min=None):
     n_seg = len(h_segments)
     n_full = len(h_segments[0])
     tpt = int(round(ticks_per_second / fs))
@@ -77,18 +105,19 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
     cw = int(round(cluster_sec * ticks_per_second))
     e = np.asarray(edges, np.float32)
     ids1 = [np.arange(coarse.n_tmpl)] * n_seg
+    kw = dict(chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
     t1h = detector_triggers(h_segments, h_psds, fs, f_low, coarse, ids1, thr1, window_sec,
-                            ticks_per_second, decim)
+                            ticks_per_second, decim, **kw)
     t1l = detector_triggers(l_segments, l_psds, fs, f_low, coarse, ids1, thr1, window_sec,
-                            ticks_per_second, decim)
+                            ticks_per_second, decim, **kw)
     c1 = timeslide_coinc(t1h, t1l, n_sh1, int(round(t_sh1_sec * ticks_per_second)), win, wrap, cw,
                          e, ticks_per_second)
     fine_ids = followup_templates(c1["coincs"], rho1, coarse.mchirp, fine.mchirp, mc_frac,
                                   seg_ticks, n_seg)
     t2h = detector_triggers(h_segments, h_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
-                            ticks_per_second)
+                            ticks_per_second, **kw)
     t2l = detector_triggers(l_segments, l_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
-                            ticks_per_second)
+                            ticks_per_second, **kw)
     c2 = timeslide_coinc(t2h, t2l, n_slides, int(round(step_sec * ticks_per_second)), win, wrap, cw,
                          e, ticks_per_second)
     return dict(stage1_h=t1h, stage1_l=t1l, coinc1=c1, fine_ids=fine_ids, trig_h=t2h, trig_l=t2l,

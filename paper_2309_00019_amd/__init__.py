@@ -6,12 +6,12 @@ is no CPU fallback).  ``hs`` is the thin binding with the C entry-point names;
 """
 from . import hs
 from .hs import (Context, PreparedBank, HsError, hs_abi_version, hs_welch_psd, hs_whiten, hs_prepare_bank,
-                 hs_matched_filter, hs_snr_series, hs_cluster_triggers, hs_timeslide_coinc, hs_followup,
+                 hs_matched_filter, hs_snr_series, hs_cluster_triggers, hs_chisq, hs_timeslide_coinc, hs_followup,
                  as_records, to_device_records, CANDIDATE, TRIGGER, COINC)
 
 hs.load_library()
 
 __all__ = ["hs", "Context", "PreparedBank", "HsError", "hs_abi_version", "hs_welch_psd", "hs_whiten",
-           "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
+           "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers", "hs_chisq",
            "hs_timeslide_coinc", "hs_followup", "as_records", "to_device_records", "CANDIDATE",
            "TRIGGER", "COINC"]

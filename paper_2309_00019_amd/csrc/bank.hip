@@ -83,6 +83,69 @@ __global__ __launch_bounds__(256) void prepare_bank_kernel(
     }
 }
 
+// Edges of p contiguous bins of equal template power pw_k = |h~_k|^2 / S_k over [lo, hi]:
+// edge l (0 < l < p) is the first bin whose cumulative power reaches l/p of the total.
+// Each thread sums a contiguous chunk, a block scan gives chunk prefixes, and the thread
+// whose prefix interval [P_t, P_t + s_t) contains the threshold walks its chunk to find the
+// crossing (if rounding leaves it past the chunk, the edge is the next chunk's first bin),
+// so every threshold is placed exactly once and deterministically.
+__global__ __launch_bounds__(256) void chisq_edges_kernel(int64_t n, int32_t kf, const double *__restrict__ psd,
+                                                          const float2 *__restrict__ raw,
+                                                          const int64_t *__restrict__ offset,
+                                                          const int32_t *__restrict__ k0,
+                                                          const int32_t *__restrict__ kstart,
+                                                          const int32_t *__restrict__ k1, int p,
+                                                          int32_t *__restrict__ edges) {
+    __shared__ double sc[256];
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t off = offset[t];
+    const int32_t a0 = k0[t], a1 = k1[t];
+    const int32_t lo = max(max(kf, kstart[t]), 1);
+    const int32_t hi = min(a1, (int32_t)(n / 2 - 1));
+    if (a1 < a0 || hi < lo || lo < a0) return;  // flagged by the preparation kernel
+    const int64_t K = (int64_t)hi - lo + 1;
+    const int64_t chunk = (K + 255) / 256;
+    const int64_t c0 = lo + tid * chunk;
+    const int64_t c1 = min((int64_t)hi, c0 + chunk - 1);
+    auto pw = [&](int64_t k) {
+        const float2 h = raw[off + (k - a0)];
+        return ((double)h.x * (double)h.x + (double)h.y * (double)h.y) / psd[k];
+    };
+    double s = 0.0;
+    for (int64_t k = c0; k <= c1; ++k) s += pw(k);
+    sc[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const double add = tid >= o ? sc[tid - o] : 0.0;
+        __syncthreads();
+        sc[tid] += add;
+        __syncthreads();
+    }
+    const double next = sc[tid];
+    const double prev = tid > 0 ? sc[tid - 1] : 0.0;
+    const double total = sc[255];
+    int32_t *e = edges + (int64_t)t * (p + 1);
+    for (int l = 1; l < p; ++l) {
+        const double T = (double)l * total / (double)p;
+        if (!(prev <= T && T < next)) continue;
+        double cum = prev;
+        int64_t where = c1 + 1;
+        for (int64_t k = c0; k <= c1; ++k) {
+            cum += pw(k);
+            if (cum >= T) {
+                where = k;
+                break;
+            }
+        }
+        e[l] = (int32_t)where;
+    }
+    if (tid == 0) {
+        e[0] = lo;
+        e[p] = hi + 1;
+    }
+}
+
 }  // namespace hs
 
 using namespace hs;
@@ -91,7 +154,7 @@ extern "C" int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, 
                                int32_t n_tmpl, const void *raw, const int64_t *offset, const int32_t *k0,
                                const int32_t *kstart, const int32_t *k1, int32_t dtype, void *spectra_out,
                                int32_t *k_lo_out, int32_t *k_hi_out, float *rho2_scale_out,
-                               double *sigma_out) {
+                               double *sigma_out, int32_t chisq_bins, int32_t *chisq_edges_out) {
     HS_REQUIRE(ctx && psd && raw && offset && k0 && kstart && k1 && spectra_out && k_lo_out && k_hi_out &&
                    rho2_scale_out && sigma_out,
                "hs_prepare_bank: null argument");
@@ -99,6 +162,8 @@ extern "C" int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, 
     HS_REQUIRE(is_pow2(n) && n >= 16 && n <= (int64_t(1) << 24), "hs_prepare_bank: n must be a power of two");
     HS_REQUIRE(fs > 0 && f_low >= 0, "hs_prepare_bank: bad fs/f_low");
     HS_REQUIRE(dtype == HS_F32 || dtype == HS_BF16 || dtype == HS_F16, "hs_prepare_bank: bad dtype %d", dtype);
+    HS_REQUIRE(chisq_bins == 0 || (chisq_bins >= 2 && chisq_bins <= 16 && chisq_edges_out),
+               "hs_prepare_bank: chisq_bins must be 0 or in [2, 16] with an edge buffer");
     if (n_tmpl == 0) return HS_OK;
     HS_HIP(hipSetDevice(ctx->device));
     int64_t kf = (int64_t)std::ceil(f_low * (double)n / fs);
@@ -124,6 +189,11 @@ extern "C" int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, 
                            (int32_t)kf, psd, r, offset, k0, kstart, k1, static_cast<uint32_t *>(spectra_out), k_lo_out,
                            k_hi_out, rho2_scale_out, sigma_out, bad, true);
     HS_HIP(hipGetLastError());
+    if (chisq_bins >= 2) {
+        hipLaunchKernelGGL(chisq_edges_kernel, dim3(n_tmpl), dim3(256), 0, ctx->stream, n, (int32_t)kf, psd, r, offset,
+                           k0, kstart, k1, (int)chisq_bins, chisq_edges_out);
+        HS_HIP(hipGetLastError());
+    }
     int32_t hbad = 0;
     HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "hs_prepare_bank: a template has an empty band or k1 < k0 / k_lo < k0");

@@ -25,7 +25,7 @@ COINC = np.dtype([("slide", "<i4"), ("tmpl", "<i4"), ("tick_h", "<i8"), ("tick_l
                   ("snr_h", "<f4"), ("snr_l", "<f4"), ("stat", "<f4"), ("snr_c", "<f4")])
 EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_welch_psd", "hs_whiten",
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
-           "hs_timeslide_coinc", "hs_followup"]
+           "hs_chisq", "hs_timeslide_coinc", "hs_followup"]
 
 
 class HsError(RuntimeError):
@@ -38,7 +38,8 @@ class _Bank(ctypes.Structure):
     _fields_ = [("n_tmpl", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("fs", ctypes.c_double), ("offset", ctypes.c_void_p), ("k0", ctypes.c_void_p),
                 ("k_lo", ctypes.c_void_p), ("k_hi", ctypes.c_void_p), ("spectra", ctypes.c_void_p),
-                ("rho2_scale", ctypes.c_void_p)]
+                ("rho2_scale", ctypes.c_void_p), ("chisq_bins", ctypes.c_int32),
+                ("chisq_edges", ctypes.c_void_p)]
 
 
 _lib = None
@@ -60,10 +61,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_abi_version": [],
         "hs_welch_psd": [P, P, I64, D, I64, P],
         "hs_whiten": [P, P, I64, D, D, P, P],
-        "hs_prepare_bank": [P, I64, D, D, P, I32, P, P, P, P, P, I32, P, P, P, P, P],
+        "hs_prepare_bank": [P, I64, D, D, P, I32, P, P, P, P, P, I32, P, P, P, P, P, I32, P],
         "hs_matched_filter": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
         "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
         "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
+        "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P],
         "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, P, I32, P, P, I64,
                                ctypes.POINTER(I64)],
         "hs_followup": [P, P, I64, F, P, I32, P, I32, D, I64, I32, P, P],
@@ -128,10 +130,12 @@ class Context:
 class PreparedBank:
     """Device arrays of a prepared bank (see hs_bank in hs.h)."""
 
-    def __init__(self, n, fs, dtype, offset, k0, k_lo, k_hi, spectra, rho2_scale, sigma, mchirp=None):
+    def __init__(self, n, fs, dtype, offset, k0, k_lo, k_hi, spectra, rho2_scale, sigma, mchirp=None,
+                 chisq_bins=0, chisq_edges=None):
         self.n, self.fs, self.dtype = int(n), float(fs), int(dtype)
         self.offset, self.k0, self.k_lo, self.k_hi = offset, k0, k_lo, k_hi
         self.spectra, self.rho2_scale, self.sigma, self.mchirp = spectra, rho2_scale, sigma, mchirp
+        self.chisq_bins, self.chisq_edges = int(chisq_bins), chisq_edges
 
     @property
     def n_tmpl(self):
@@ -139,14 +143,16 @@ class PreparedBank:
 
     def struct(self) -> _Bank:
         return _Bank(self.n_tmpl, self.dtype, self.n, self.fs, _ptr(self.offset), _ptr(self.k0),
-                     _ptr(self.k_lo), _ptr(self.k_hi), _ptr(self.spectra), _ptr(self.rho2_scale))
+                     _ptr(self.k_lo), _ptr(self.k_hi), _ptr(self.spectra), _ptr(self.rho2_scale),
+                     self.chisq_bins, _ptr(self.chisq_edges))
 
     @staticmethod
-    def allocate(n, fs, dtype, offset, k0, total_elems, device):
+    def allocate(n, fs, dtype, offset, k0, total_elems, device, chisq_bins=0):
         """Empty bank with the given layout (offset/k0 host arrays)."""
         T = len(offset)
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         spectra = torch.empty(int(total_elems) * ELEM_BYTES[dt], dtype=torch.uint8, device=device)
+        edges = torch.empty((T, chisq_bins + 1), dtype=torch.int32, device=device) if chisq_bins else None
         return PreparedBank(n, fs, dt,
                             torch.as_tensor(np.asarray(offset, np.int64), device=device),
                             torch.as_tensor(np.asarray(k0, np.int32), device=device),
@@ -154,7 +160,8 @@ class PreparedBank:
                             torch.empty(T, dtype=torch.int32, device=device),
                             spectra,
                             torch.empty(T, dtype=torch.float32, device=device),
-                            torch.empty(T, dtype=torch.float64, device=device))
+                            torch.empty(T, dtype=torch.float64, device=device),
+                            chisq_bins=chisq_bins, chisq_edges=edges)
 
 
 def mf_batch_templates(n: int, n_ids: int) -> int:
@@ -190,7 +197,7 @@ def hs_whiten(ctx: Context, strain, fs: float, f_low: float, psd, out=None):
 
 
 def hs_prepare_bank(ctx: Context, n: int, fs: float, f_low: float, psd, raw, offset, k0, kstart, k1,
-                    dtype="f32", bank: PreparedBank = None, t0: int = 0, elem0: int = 0):
+                    dtype="f32", bank: PreparedBank = None, t0: int = 0, elem0: int = 0, chisq_bins: int = 8):
     """Prepare templates into ``bank`` (allocated with the same layout as ``raw``).
 
     ``raw`` complex64 device tensor; offset/k0/kstart/k1 device tensors relative to ``raw``.
@@ -207,15 +214,20 @@ def hs_prepare_bank(ctx: Context, n: int, fs: float, f_low: float, psd, raw, off
                             torch.empty(T, dtype=torch.int32, device=raw.device),
                             torch.empty(raw.numel() * ELEM_BYTES[dt], dtype=torch.uint8, device=raw.device),
                             torch.empty(T, dtype=torch.float32, device=raw.device),
-                            torch.empty(T, dtype=torch.float64, device=raw.device))
+                            torch.empty(T, dtype=torch.float64, device=raw.device),
+                            chisq_bins=chisq_bins,
+                            chisq_edges=torch.empty((T, chisq_bins + 1), dtype=torch.int32, device=raw.device)
+                            if chisq_bins else None)
     eb = ELEM_BYTES[bank.dtype]
+    pb = bank.chisq_bins
+    edges_ptr = ctypes.c_void_p(bank.chisq_edges.data_ptr() + 4 * (pb + 1) * t0) if pb else None
     sp = bank.spectra.data_ptr() + elem0 * eb
     _check(_lib.hs_prepare_bank(ctx.handle, n, fs, f_low, _ptr(psd), T, _ptr(raw), _ptr(offset), _ptr(k0),
                                 _ptr(kstart), _ptr(k1), bank.dtype, ctypes.c_void_p(sp),
                                 ctypes.c_void_p(bank.k_lo.data_ptr() + 4 * t0),
                                 ctypes.c_void_p(bank.k_hi.data_ptr() + 4 * t0),
                                 ctypes.c_void_p(bank.rho2_scale.data_ptr() + 4 * t0),
-                                ctypes.c_void_p(bank.sigma.data_ptr() + 8 * t0)), "hs_prepare_bank")
+                                ctypes.c_void_p(bank.sigma.data_ptr() + 8 * t0), pb, edges_ptr), "hs_prepare_bank")
     return bank
 
 
@@ -274,6 +286,20 @@ def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: 
         _check(st, "hs_cluster_triggers")
         return out[: cnt.value]
     raise HsError(HS_EOVERFLOW, "hs_cluster_triggers: overflow after resize")
+
+
+def hs_chisq(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, trig, seg_t0: int = 0,
+             ticks_per_sample: int = 1, rho_min: float = 0.0, out=None):
+    """Returns (float32 [n_trig] chi2_r, int32 [n_trig, 6] triggers with snr re-weighted by Eq. (4))."""
+    _dev(spec, torch.complex64, "spec")
+    _dev(trig, torch.int32, "trig")
+    n_trig = trig.shape[0]
+    chi = torch.empty(n_trig, dtype=torch.float32, device=trig.device)
+    out = torch.empty_like(trig) if out is None else out
+    bs = bank.struct()
+    _check(_lib.hs_chisq(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(trig), n_trig, seg_t0,
+                         ticks_per_sample, float(rho_min), _ptr(chi), _ptr(out)), "hs_chisq")
+    return chi, out
 
 
 def hs_timeslide_coinc(ctx: Context, trig_h, trig_l, n_tmpl: int, n_slides: int, step: int, window: int,

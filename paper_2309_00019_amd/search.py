@@ -41,6 +41,7 @@ class SearchConfig:
     coinc_window_sec: float = 0.015
     cluster_sec: float = 1.0      # per-slide coincidence clustering window
     edges: tuple = (6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0, 14.0, 16.0, 20.0)
+    chisq_rho_min: float = 5.5    # triggers at or above this SNR get the chi-square re-weighting (None: off)
 
 
 @dataclass
@@ -102,8 +103,12 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
             continue
         f = lambda: hs.hs_matched_filter(ctx, specs[s], n, fs, bank, ids, thr)
         cand = timer.run(f, n, ids, bank) if timer else f()
-        parts.append(hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks,
-                                            ticks_per_sample=tps))
+        trig = hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks, ticks_per_sample=tps)
+        if cfg.chisq_rho_min is not None and bank.chisq_bins:
+            # Eq. (4): the coincidence statistic combines re-weighted SNRs
+            _, trig = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
+                                  rho_min=cfg.chisq_rho_min, out=trig)
+        parts.append(trig)
     if not parts:
         return torch.zeros((0, 6), dtype=torch.int32, device=specs.device)
     return torch.cat(parts) if len(parts) > 1 else parts[0]

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_abi_version_and_error_string_without_gpu():
     from paper_2309_00019_amd import hs
     lib = hs.load_library()
-    assert lib.hs_abi_version() == 1
+    assert lib.hs_abi_version() == 2
     assert isinstance(lib.hs_last_error(), bytes)
 
 
@@ -40,7 +40,7 @@ def test_record_layouts_match_header():
     assert hs.COINC.fields["stat"][1] == 32
     assert hs.CANDIDATE == synth.CANDIDATE_DTYPE and hs.TRIGGER == synth.TRIGGER_DTYPE
     assert hs.COINC == synth.COINC_DTYPE
-    assert ctypes.sizeof(hs._Bank) == 4 + 4 + 8 + 8 + 6 * 8
+    assert ctypes.sizeof(hs._Bank) == 4 + 4 + 8 + 8 + 6 * 8 + 8 + 8
 
 
 def test_argument_errors_need_no_gpu():
