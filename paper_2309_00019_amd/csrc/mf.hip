@@ -31,16 +31,33 @@ static constexpr int PA_LDS_LSTRIDE = 16 * 16 + 16;  // float2 per l-block (padd
 static constexpr int PB_THREADS = 128;                // pass-B workgroup size
 static constexpr int MF_STRIPES = 64;                 // candidate lists (power of two)
 
-// Concatenates the striped candidate lists into the caller's buffer (in stripe order).
+// Candidate lists: MF_STRIPES lists of stripe_cap records followed by one spill list of
+// spill_cap records; count[0..MF_STRIPES-1] are the per-list reservation counters (they may run
+// past stripe_cap -- the excess went to the spill list) and count[MF_STRIPES] the spill counter.
+// mf_compact concatenates the lists (stripe order, then the spill list) into the caller's buffer.
 __global__ __launch_bounds__(256) void mf_compact(const hs_candidate *__restrict__ buf,
                                                   const unsigned long long *__restrict__ count, int64_t stripe_cap,
-                                                  hs_candidate *__restrict__ out, int64_t cap) {
-    const int s = blockIdx.y;
+                                                  int64_t spill_cap, hs_candidate *__restrict__ out, int64_t cap) {
+    const int s = blockIdx.y;  // 0..MF_STRIPES (the last one is the spill list)
     unsigned long long off = 0;
     for (int q = 0; q < s; ++q) off += count[q] < (unsigned long long)stripe_cap ? count[q] : stripe_cap;
-    const unsigned long long n = count[s] < (unsigned long long)stripe_cap ? count[s] : stripe_cap;
+    const unsigned long long lim = s < MF_STRIPES ? (unsigned long long)stripe_cap : (unsigned long long)spill_cap;
+    const unsigned long long n = count[s] < lim ? count[s] : lim;
+    const hs_candidate *src = buf + (size_t)s * stripe_cap;
     for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull)
-        if (off + i < (unsigned long long)cap) out[off + i] = buf[(size_t)s * stripe_cap + i];
+        if (off + i < (unsigned long long)cap) out[off + i] = src[i];
+}
+
+// Stores record o at reservation index idx of stripe list `stripe`, spilling past its capacity.
+__device__ __forceinline__ void mf_store_one(hs_candidate *lists, unsigned long long *count, int stripe,
+                                             int64_t stripe_cap, int64_t spill_cap, unsigned long long idx,
+                                             const hs_candidate &o) {
+    if (idx < (unsigned long long)stripe_cap) {
+        lists[(size_t)stripe * stripe_cap + idx] = o;
+    } else {
+        const unsigned long long j = atomicAdd(&count[MF_STRIPES], 1ull);
+        if (j < (unsigned long long)spill_cap) lists[(size_t)MF_STRIPES * stripe_cap + j] = o;
+    }
 }
 
 __global__ void mf_validate(const int32_t *__restrict__ ids, int32_t n_ids, int32_t n_tmpl,
@@ -209,7 +226,7 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
                                                  const float2 *__restrict__ twN1, const int32_t *__restrict__ bad,
                                                  hs_candidate *__restrict__ cand,
                                                  unsigned long long *__restrict__ counter, int64_t cap,
-                                                 float2 *__restrict__ zout) {
+                                                 int64_t spill_cap, float2 *__restrict__ zout) {
     constexpr int LPR = N1 / 16;    // lanes per row
     constexpr int RPB = PB_THREADS / LPR;  // rows per block
     constexpr int R2 = PassBPlan<N1>::R2, R3 = PassBPlan<N1>::R3;
@@ -217,7 +234,7 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
     constexpr int LDS_N = N1 > 16 ? RPB * ROW : 1024;
     __shared__ float2 lds[LDS_N];
     __shared__ unsigned int s_count;
-    __shared__ unsigned long long s_base;
+    __shared__ unsigned long long s_base, s_spill;
     if (*bad) return;
     if (threadIdx.x == 0) s_count = 0;
     const int tb = blockIdx.y;
@@ -260,13 +277,12 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
         // wavefront reserves slots with one LDS atomic per ballot, then the workgroup reserves
         // its block of one of MF_STRIPES candidate lists with a single atomic and writes it out
         // contiguously (striping keeps same-address atomics from serialising across the GPU;
-        // the lists are concatenated after the last batch).  Slots beyond the staging capacity
-        // (only near very loud signals) go straight to the list, one atomic per lane.
+        // the lists are concatenated after the last batch; records past a list's capacity go to
+        // the shared spill list).  Slots beyond the staging capacity (only near very loud
+        // signals) go straight to the lists, one atomic per lane.
         constexpr int STAGE = LDS_N / 2;  // hs_candidate = 2 float2
         hs_candidate *stage = reinterpret_cast<hs_candidate *>(lds);
-        const unsigned int stripe = (blockIdx.y * gridDim.x + blockIdx.x) & (MF_STRIPES - 1);
-        counter += stripe;
-        cand += (size_t)stripe * (size_t)cap;
+        const int stripe = (int)((blockIdx.y * gridDim.x + blockIdx.x) & (MF_STRIPES - 1));
         const int lane = __lane_id();
         const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         __syncthreads();
@@ -292,19 +308,32 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
                     if (slot < (unsigned int)STAGE) {
                         stage[slot] = o;
                     } else {
-                        const unsigned long long idx = atomicAdd(counter, 1ull);
-                        if (idx < (unsigned long long)cap) cand[idx] = o;
+                        const unsigned long long idx = atomicAdd(&counter[stripe], 1ull);
+                        mf_store_one(cand, counter, stripe, cap, spill_cap, idx, o);
                     }
                 }
             }
         }
         __syncthreads();
         const unsigned int k = s_count < (unsigned int)STAGE ? s_count : (unsigned int)STAGE;
-        if (threadIdx.x == 0) s_base = k ? atomicAdd(counter, (unsigned long long)k) : 0ull;
+        if (threadIdx.x == 0) {
+            const unsigned long long b = k ? atomicAdd(&counter[stripe], (unsigned long long)k) : 0ull;
+            // records with reservation index >= cap spill; reserve them in one step
+            const unsigned long long first_over = b > (unsigned long long)cap ? b : (unsigned long long)cap;
+            const unsigned long long over = (b + k > (unsigned long long)cap) ? b + k - first_over : 0ull;
+            s_base = b;
+            s_spill = over ? atomicAdd(&counter[MF_STRIPES], over) : 0ull;
+        }
         __syncthreads();
+        const unsigned long long first_over = s_base > (unsigned long long)cap ? s_base : (unsigned long long)cap;
         for (unsigned int i = threadIdx.x; i < k; i += PB_THREADS) {
             const unsigned long long idx = s_base + i;
-            if (idx < (unsigned long long)cap) cand[idx] = stage[i];
+            if (idx < (unsigned long long)cap) {
+                cand[(size_t)stripe * cap + idx] = stage[i];
+            } else {
+                const unsigned long long j = s_spill + (idx - first_over);
+                if (j < (unsigned long long)spill_cap) cand[(size_t)MF_STRIPES * cap + j] = stage[i];
+            }
         }
     }
 }
@@ -312,11 +341,11 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
 template <bool WRITE_Z>
 static int launch_pass_b(hs_ctx *ctx, int N1, dim3 grid, const float2 *Y, const float *r2s, const int32_t *ids,
                          int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
-                         unsigned long long *counter, int64_t cap, float2 *zout) {
+                         unsigned long long *counter, int64_t cap, int64_t spill_cap, float2 *zout) {
 #define HS_PB(NN)                                                                                         \
     case NN:                                                                                              \
         hipLaunchKernelGGL((mf_pass_b<NN, WRITE_Z>), grid, dim3(PB_THREADS), 0, ctx->stream, Y, r2s, ids, id0, thr2, \
-                           twN1, bad, cand, counter, cap, zout);                                          \
+                           twN1, bad, cand, counter, cap, spill_cap, zout);                               \
         break;
     switch (N1) {
         HS_PB(16) HS_PB(32) HS_PB(64) HS_PB(128) HS_PB(256) HS_PB(512) HS_PB(1024) HS_PB(2048)
@@ -361,20 +390,21 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
     HS_TRY(twiddles_f32(ctx, ilog2(N1), &twN1));
 
-    // Striped candidate lists: MF_STRIPES lists of stripe_cap records each (the caller's
-    // capacity spread over the stripes, plus slack for uneven filling).
-    const int64_t stripe_cap = WRITE_Z ? 1 : cap / MF_STRIPES + 4096;
+    // Striped candidate lists: MF_STRIPES lists sharing the caller's capacity equally plus a spill
+    // list as large as the whole capacity, so every distribution of up to `cap` candidates fits.
+    const int64_t stripe_cap = WRITE_Z ? 0 : cap / MF_STRIPES;
+    const int64_t spill_cap = WRITE_Z ? 0 : cap;
     float2 *Y;
     unsigned long long *counter;
     hs_candidate *sbuf;
     int32_t *bad;
     Carver cv;
     cv.add(&Y, (size_t)tb_max * n);
-    cv.add(&counter, MF_STRIPES);
-    cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap);
+    cv.add(&counter, MF_STRIPES + 1);
+    cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap + spill_cap + 1);
     cv.add(&bad, 1);
     HS_TRY(cv.commit(ctx));
-    HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), MF_STRIPES, 0));
+    HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), MF_STRIPES + 1, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
     hipLaunchKernelGGL(mf_validate, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
                        bank->n_tmpl, bank->k0, bank->k_lo, bank->k_hi, n / 2, bad);
@@ -405,35 +435,26 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
         HS_HIP(hipGetLastError());
         const dim3 gb((unsigned)(512 * N1 / (16 * PB_THREADS)), (unsigned)tb);  // 512 rows / rows per block
         HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, gb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, sbuf,
-                                      counter, stripe_cap, zout));
+                                      counter, stripe_cap, spill_cap, zout));
     }
     if (!WRITE_Z && cap > 0) {
-        hipLaunchKernelGGL(mf_compact, dim3(16, MF_STRIPES), dim3(256), 0, ctx->stream, sbuf, counter, stripe_cap,
-                           cand, cap);
+        hipLaunchKernelGGL(mf_compact, dim3(16, MF_STRIPES + 1), dim3(256), 0, ctx->stream, sbuf, counter,
+                           stripe_cap, spill_cap, cand, cap);
         HS_HIP(hipGetLastError());
     }
-    unsigned long long hc[MF_STRIPES];
+    unsigned long long hc[MF_STRIPES + 1];
     int32_t hbad = 0;
     HS_TRY(read_back(ctx, counter, hc, sizeof(hc)));
     HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
                hbad);
     if (!WRITE_Z) {
-        unsigned long long total = 0, most = 0;
-        for (int s = 0; s < MF_STRIPES; ++s) {
-            total += hc[s];
-            most = hc[s] > most ? hc[s] : most;
-        }
+        unsigned long long total = 0;
+        for (int s = 0; s < MF_STRIPES; ++s) total += hc[s];
         *n_cand = (int64_t)total;
         if ((int64_t)total > cap)
             return set_error(HS_EOVERFLOW, "matched filter: %llu candidates exceed capacity %lld", total,
                              (long long)cap);
-        if ((int64_t)most > stripe_cap) {
-            // one list filled up although the total fits: ask for room that fits the fullest list
-            *n_cand = (int64_t)(most * MF_STRIPES);
-            return set_error(HS_EOVERFLOW, "matched filter: candidate list %llu > %lld; retry with capacity %lld",
-                             most, (long long)stripe_cap, (long long)*n_cand);
-        }
     }
     return HS_OK;
 }

@@ -356,3 +356,27 @@ def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind):
         worst = max(worst, abs(rw["snr"][i] / r_ref - 1.0))
     assert worst < 2e-4
     assert np.any(chi > 3.0)  # the glitches are flagged
+
+
+def test_exact_capacity_holds_unevenly_spread_candidates(ctx):
+    """Candidates concentrated in time (a loud glitch, two templates) must fit a capacity equal
+    to their count: the striped lists spill instead of overflowing."""
+    import ctypes
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("exact capacity")
+    n, fs, f_low = 2 ** 15, 2048.0, 20.0
+    bank = _bank_for("tau", n, fs, f_low, count=2, seed=19)
+    t = np.arange(n) / fs
+    tau = 9.0 / (np.sqrt(2) * np.pi * 150.0)
+    g = 2e4 * np.exp(-((t - 5.0) / tau) ** 2) * np.sin(2 * np.pi * 150.0 * (t - 5.0))
+    s = (_strain(19, 0, n, fs, f_low) + g).astype(np.float32)
+    psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(2, dtype=torch.int32, device=ctx.device)
+    full = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 3.0), hs.CANDIDATE)
+    assert len(full) > 500
+    tight = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 3.0, cap=len(full)), hs.CANDIDATE)
+    key = lambda r: sorted(zip(r["tpos"].tolist(), r["m"].tolist()))
+    assert key(tight) == key(full)
