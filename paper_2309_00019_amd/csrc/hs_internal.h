@@ -64,7 +64,7 @@ struct hs_ctx {
     // Twiddle tables keyed by log2(length).
     std::map<int, hs::Twiddles> tw;
     // Matched-filter batch budget for the pass-A/pass-B intermediate (bytes).
-    size_t mf_batch_bytes = size_t(256) << 20;
+    size_t mf_batch_bytes = size_t(128) << 20;
 };
 
 namespace hs {

@@ -167,7 +167,7 @@ class PreparedBank:
 def mf_batch_templates(n: int, n_ids: int) -> int:
     """Templates per pass-A/pass-B launch in hs_matched_filter (same rule as the library)."""
     mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
-    budget = (mb << 20) if mb > 0 else (256 << 20)
+    budget = (mb << 20) if mb > 0 else (128 << 20)
     return max(1, min(65535, n_ids, budget // (n * 8)))
 
 
