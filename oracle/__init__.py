@@ -18,6 +18,9 @@ NumPy/SciPy, citing the passage of the paper it follows:
 * ``followup``  -- stage-1 selection and neighbourhood union (Sec. III)
 * ``pipeline``  -- flat and two-stage hierarchical searches (Secs. II-III)
 * ``costmodel`` -- matched-filter speed-up model (Sec. V, Eq. (8))
+* ``chisq``     -- power-consistency chi-square, its per-bin terms, re-weighted SNR (Eq. (4))
+* ``proposer``  -- learned follow-up proposer: coincidence features, MLP forward/backward,
+                   Adam, cell selection and the cell-restricted neighbourhood rule
 
 Where the paper is silent or garbled the reading taken is stated in the
 docstring of the function that takes it.
@@ -37,6 +40,7 @@ __all__ = [
     "timeslide_coinc", "false_alarm_rate", "coinc_stat", "followup_templates",
     "flat_search", "hierarchical_search", "speedup_eq8",
 ]
-from .chisq import chisq_bin_edges, chisq_at, reweighted_snr  # noqa: E402
+from .chisq import chisq_bin_edges, chisq_at, bin_snrs, chisq_terms, reweighted_snr  # noqa: E402
+from . import proposer  # noqa: E402
 
-__all__ += ["chisq_bin_edges", "chisq_at", "reweighted_snr"]
+__all__ += ["chisq_bin_edges", "chisq_at", "bin_snrs", "chisq_terms", "reweighted_snr", "proposer"]

@@ -34,8 +34,8 @@ def chisq_bin_edges(htilde, psd, k_lo: int, k_hi: int, p: int) -> np.ndarray:
     return np.asarray(edges, np.int64)
 
 
-def chisq_at(stilde, htilde, psd, n: int, fs: float, sigma: float, m: int, edges) -> tuple:
-    """(chi2_r, z) of one template at sample m for the given bin edges."""
+def bin_snrs(stilde, htilde, psd, n: int, fs: float, sigma: float, m: int, edges) -> np.ndarray:
+    """The p band-limited complex SNRs z_l of one template at sample m."""
     df = fs / n
     p = len(edges) - 1
     zl = np.zeros(p, np.complex128)
@@ -43,9 +43,22 @@ def chisq_at(stilde, htilde, psd, n: int, fs: float, sigma: float, m: int, edges
         k = np.arange(edges[l], edges[l + 1])
         q = np.asarray(stilde[k], np.complex128) * np.conj(np.asarray(htilde[k], np.complex128)) / psd[k]
         zl[l] = np.sum(q * np.exp(2j * np.pi * (k * m % n) / n)) * (4.0 * df / sigma)
-    z = zl.sum()
-    chi2 = p * np.sum(np.abs(zl - z / p) ** 2)
-    return chi2 / (2 * p - 2), z
+    return zl
+
+
+def chisq_terms(zl) -> np.ndarray:
+    """Per-bin terms X_l = p |z_l - z/p|^2 (their sum is chi2)."""
+    zl = np.asarray(zl, np.complex128)
+    p = len(zl)
+    return p * np.abs(zl - zl.sum() / p) ** 2
+
+
+def chisq_at(stilde, htilde, psd, n: int, fs: float, sigma: float, m: int, edges) -> tuple:
+    """(chi2_r, z) of one template at sample m for the given bin edges."""
+    zl = bin_snrs(stilde, htilde, psd, n, fs, sigma, m, edges)
+    p = len(zl)
+    chi2 = p * np.sum(np.abs(zl - zl.sum() / p) ** 2)
+    return chi2 / (2 * p - 2), zl.sum()
 
 
 def reweighted_snr(rho, chi2_r):

@@ -23,7 +23,8 @@ from .filter import filter_bank, triggers_from_candidates
 from .coinc import timeslide_coinc
 from .followup import followup_templates
 from .filter import band_edges, template_sigma
-from .chisq import chisq_bin_edges, chisq_at, reweighted_snr
+from .chisq import chisq_bin_edges, bin_snrs, chisq_terms, reweighted_snr
+from . import proposer as _proposer
 
 
 def _concat(parts):
@@ -36,6 +37,7 @@ def reweight_triggers(tr, st, psd, n, fs, f_low, bank, chisq_bins: int, rho_min:
     (chi-square per ``chisq``); adds columns snr_raw and chisq."""
     snr = np.asarray(tr["snr"], np.float64)
     chi = np.zeros(len(snr))
+    bins = np.zeros((len(snr), chisq_bins))
     for i in np.nonzero(snr >= rho_min)[0]:
         t = int(tr["tmpl"][i])
         h = bank.spectrum(t)
@@ -43,10 +45,13 @@ def reweight_triggers(tr, st, psd, n, fs, f_low, bank, chisq_bins: int, rho_min:
         sig = template_sigma(h, psd, n, fs, k_lo, k_hi)
         e = chisq_bin_edges(h, psd, k_lo, k_hi, chisq_bins)
         m = (int(tr["tick"][i]) - seg_t0) // tps
-        chi[i] = chisq_at(st, h, psd, n, fs, sig, m, e)[0]
+        zl = bin_snrs(st, h, psd, n, fs, sig, m, e)
+        bins[i] = chisq_terms(zl)
+        chi[i] = bins[i].sum() / (2 * chisq_bins - 2)
     out = dict(tr)
     out["snr_raw"] = snr
     out["chisq"] = chi
+    out["bins"] = bins
     out["snr"] = reweighted_snr(snr, chi)
     return out
 
@@ -95,7 +100,9 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                         decim=4, thr1=3.5, thr2=4.0, window_sec=1.0, ticks_per_second=51200,
                         n_sh1=16, t_sh1_sec=15.0, rho1=7.0, mc_frac=0.05,
                         n_slides=2000, step_sec=0.1, coinc_window_sec=0.015, cluster_sec=1.0,
-                        edges=(8.0,), chisq_bins=8, chisq_rho_min=None):
+                        edges=(8.0,), chisq_bins=8, chisq_rho_min=None, proposer=None):
+    """``proposer`` = (model, q_edges, p_cum) switches the follow-up to the learned cell rule
+    (``proposer`` module); the bank objects then need ``q`` (mass ratio m1/m2 >= 1) as well."""
     n_seg = len(h_segments)
     n_full = len(h_segments[0])
     tpt = int(round(ticks_per_second / fs))
@@ -112,8 +119,18 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                             ticks_per_second, decim, **kw)
     c1 = timeslide_coinc(t1h, t1l, n_sh1, int(round(t_sh1_sec * ticks_per_second)), win, wrap, cw,
                          e, ticks_per_second)
-    fine_ids = followup_templates(c1["coincs"], rho1, coarse.mchirp, fine.mchirp, mc_frac,
-                                  seg_ticks, n_seg)
+    if proposer is None:
+        fine_ids = followup_templates(c1["coincs"], rho1, coarse.mchirp, fine.mchirp, mc_frac,
+                                      seg_ticks, n_seg)
+    else:
+        # learned proposer: cells of each followed neighbourhood ranked by the MLP
+        model, q_edges, p_cum = proposer
+        cc = c1["coincs"]
+        feats = _proposer.features(cc, t1h, t1l, coarse.mchirp, coarse.q, int(round(t_sh1_sec * ticks_per_second)),
+                                   wrap, ticks_per_second, chisq_bins)
+        masks = _proposer.select_cells(_proposer.forward(model, feats)[0], p_cum) if len(feats) else np.zeros(0, np.uint64)
+        fine_ids = _proposer.followup_cells(cc, rho1, coarse.mchirp, fine.mchirp, fine.q, q_edges, mc_frac,
+                                            seg_ticks, n_seg, masks)
     t2h = detector_triggers(h_segments, h_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
                             ticks_per_second, **kw)
     t2l = detector_triggers(l_segments, l_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
