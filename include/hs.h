@@ -207,12 +207,13 @@ int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, i
  *   spec, bank as for hs_matched_filter (bank prepared with chisq_bins >= 2);
  *   trig device hs_trigger [n_trig] of this segment (tmpl in [0, n_tmpl));
  *   chisq_out device float [n_trig]; trig_out device hs_trigger [n_trig]
- *   (may alias trig).
+ *   (may alias trig); bins_out device float [n_trig][p] or NULL: the per-bin
+ *   terms X_l = p |z_l - z/p|^2 (sum over l = chi2; zero for copied triggers).
  * HS_EINVAL if a trigger's tmpl or tick does not belong to this bank/segment.
  */
 int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
              const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
-             float rho_min, float *chisq_out, hs_trigger *trig_out);
+             float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out);
 
 /*
  * Two-detector coincidence over time slides (Sec. I; Sec. II, Eq. (6)).
@@ -251,6 +252,91 @@ int hs_followup(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_min,
                 const double *coarse_mchirp, int32_t n_coarse, const double *fine_mchirp,
                 int32_t n_fine, double frac, int64_t seg_ticks, int32_t n_seg, int32_t *fine_ids,
                 int32_t *n_ids);
+
+/* ---------------------------------------------------------------------------
+ * Learned follow-up proposer (an addition on top of Sec. III's neighbourhood
+ * rule).  The neighbourhood of a followed coarse template c (every fine f with
+ * |mchirp_f - mchirp_c| <= frac mchirp_c) is split into 64 cells:
+ *   u = (mchirp_f - mchirp_c) / (frac mchirp_c)          (float64, this order)
+ *   cell = 4 min(15, max(0, floor((u + 1) * 8))) + #{q_edges[e] <= q_f}
+ * and an MLP scores the cells from 16 features of the stage-1 coincidence;
+ * only the smallest set of most probable cells whose softmax probabilities
+ * sum to at least p_cum is re-filtered.  All 64 cells = the plain rule.
+ *
+ * Model: device float [HS_MLP_MODEL] =
+ *   [mu (16), inv_std (16), W1 16x128, b1, W2 128x128, b2, W3 128x128, b3,
+ *    W4 128x64, b4], each W row-major [input][output]; the HS_MLP_PARAMS values
+ * after the first 32 are trained.  h0 = (x - mu) inv_std, h_i = relu(h_{i-1}
+ * W_i + b_i) (i = 1..3), logits = h3 W4 + b4.  FP32 throughout.
+ * ------------------------------------------------------------------------- */
+#define HS_MLP_FEATURES 16
+#define HS_MLP_CELLS 64
+#define HS_MLP_PARAMS 43456
+#define HS_MLP_MODEL (32 + HS_MLP_PARAMS)
+
+/*
+ * Features of coincidences (float32 [n_c][16], computed in float64):
+ *   0 snr_h, 1 snr_l, 2 snr_c (of the coincidence record),
+ *   3 (chi2_r,H + chi2_r,L) / 2,
+ *   4..11 (X_H,l + X_L,l) / (2 (2p - 2) / p)   (hs_chisq bins_out, p = 8),
+ *   12 coarse_mchirp[tmpl], 13 coarse_q[tmpl],
+ *   14 ((tick_h - tick_l - slide step + wrap/2) mod wrap - wrap/2) / ticks_per_second,
+ *   15 phase_H - phase_L wrapped into (-pi, pi] (IEEE remainder by 2 pi).
+ * The H (L) trigger of a coincidence is the record of trig_h (trig_l) with
+ * the coincidence's tmpl and tick_h (tick_l); trigger arrays must be sorted
+ * by (seg, tmpl, tick) with seg = floor(tick / seg_ticks), as produced by
+ * hs_cluster_triggers per segment (increasing template ids) concatenated in
+ * segment order.  chisq_* [n] and bins_* [n][8] are hs_chisq's outputs for
+ * those triggers.  All arrays device; HS_EINVAL if chisq_bins != 8, a
+ * template id is outside [0, n_coarse) or a trigger is missing.
+ */
+int hs_proposer_features(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, const hs_trigger *trig_h,
+                         int64_t n_h, const float *chisq_h, const float *bins_h,
+                         const hs_trigger *trig_l, int64_t n_l, const float *chisq_l,
+                         const float *bins_l, int32_t chisq_bins, int64_t seg_ticks,
+                         const double *coarse_mchirp, const double *coarse_q, int32_t n_coarse,
+                         int64_t step, int64_t wrap, int64_t ticks_per_second, float *feat_out);
+
+/* MLP logits: model device [HS_MLP_MODEL], x device float [n][16],
+ * logits_out device float [n][64]. */
+int hs_mlp_forward(hs_ctx *ctx, const float *model, const float *x, int64_t n, float *logits_out);
+
+/*
+ * One training step on a batch: loss = mean over the batch of the softmax
+ * cross-entropy of the logits against labels (cells in [0, 64)); gradient by
+ * backpropagation (sums in a fixed order: deterministic); then Adam
+ * (Kingma & Ba 2015, Algorithm 1; beta1 0.9, beta2 0.999, eps 1e-8) at step
+ * t >= 1 with learning rate lr on the trained values model[32..].
+ *   model, adam_m, adam_v device float ([HS_MLP_MODEL], [HS_MLP_PARAMS] x 2;
+ *   the moments start at zero); x device [n][16]; labels device int32 [n];
+ *   grad_out device float [HS_MLP_PARAMS] or NULL (receives the gradient);
+ *   loss_out host float (loss before the update).
+ * HS_EINVAL on a label outside [0, 64), t < 1 or n < 1.
+ */
+int hs_mlp_train_step(hs_ctx *ctx, float *model, float *adam_m, float *adam_v, int64_t t, float lr,
+                      const float *x, const int32_t *labels, int64_t n, float *grad_out,
+                      float *loss_out);
+
+/*
+ * Cell selection: per row, softmax of the logits (float32), cells taken in
+ * decreasing probability (equal probabilities: lower cell first) until the
+ * running sum reaches p_cum (all 64 if it never does).  mask_out device
+ * uint64 [n], bit c = cell c selected.
+ */
+int hs_mlp_propose(hs_ctx *ctx, const float *model, const float *x, int64_t n, float p_cum,
+                   uint64_t *mask_out);
+
+/*
+ * Follow-up restricted to cells: as hs_followup, but a followed coincidence i
+ * adds only the fine templates of its neighbourhood whose cell bit is set in
+ * cell_mask[i] (cells as above).  fine_q device double [n_fine] (m1/m2);
+ * q_edges host double [3]; cell_mask device uint64 [n_c].
+ */
+int hs_followup_cells(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_min,
+                      const double *coarse_mchirp, int32_t n_coarse, const double *fine_mchirp,
+                      const double *fine_q, int32_t n_fine, double frac, const double *q_edges,
+                      const uint64_t *cell_mask, int64_t seg_ticks, int32_t n_seg,
+                      int32_t *fine_ids, int32_t *n_ids);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhs.so")
 ARCH = "gfx950"
 
-SOURCES = ["ctx.hip", "whiten.hip", "bank.hip", "mf.hip", "cluster.hip", "chisq.hip", "coinc.hip", "followup.hip"]
+SOURCES = ["ctx.hip", "whiten.hip", "bank.hip", "mf.hip", "cluster.hip", "chisq.hip", "coinc.hip", "followup.hip", "proposer.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit (the host pass
 # ignores the feature with a warning).

@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void chisq_kernel(const float2 *__restrict__ d
                                                     const hs_trigger *trig, int32_t n_tmpl, int64_t seg_t0,
                                                     int64_t tps, float rho_min, const float2 *__restrict__ twlo,
                                                     const float2 *__restrict__ twhi, float *__restrict__ chisq_out,
-                                                    hs_trigger *trig_out, int32_t *__restrict__ bad) {
+                                                    hs_trigger *trig_out, float *__restrict__ bins_out,
+                                                    int32_t *__restrict__ bad) {
     __shared__ double red[4][2 * P];
     const int64_t i = blockIdx.x;
     const hs_trigger tr = trig[i];
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(256) void chisq_kernel(const float2 *__restrict__ d
             chisq_out[i] = 0.0f;
             trig_out[i] = tr;
         }
+        if (bins_out && tid < P) bins_out[i * P + tid] = 0.0f;
         return;
     }
     const int t = tr.tmpl;
@@ -94,6 +96,7 @@ __global__ __launch_bounds__(256) void chisq_kernel(const float2 *__restrict__ d
         for (int l = 0; l < P; ++l) {
             const double dr = zr[l] - Zr / P, di = zi[l] - Zi / P;
             chi2 += dr * dr + di * di;
+            if (bins_out) bins_out[i * P + l] = (float)(P * (dr * dr + di * di));
         }
         const double c = chi2 * P / (2.0 * P - 2.0);
         double rw = (double)tr.snr;
@@ -108,14 +111,15 @@ __global__ __launch_bounds__(256) void chisq_kernel(const float2 *__restrict__ d
 template <typename ST>
 static int launch_chisq(hs_ctx *ctx, int p, int64_t n_trig, const float2 *d, int64_t n, const hs_bank *bank,
                         const hs_trigger *trig, int64_t seg_t0, int64_t tps, float rho_min, const float2 *twlo,
-                        const float2 *twhi, float *chisq_out, hs_trigger *trig_out, int32_t *bad) {
+                        const float2 *twhi, float *chisq_out, hs_trigger *trig_out, float *bins_out,
+                        int32_t *bad) {
     const auto *sp = static_cast<const typename ST::elem *>(bank->spectra);
 #define HS_CQ(PP)                                                                                                  \
     case PP:                                                                                                       \
         hipLaunchKernelGGL((chisq_kernel<ST, PP>), dim3((unsigned)n_trig), dim3(256), 0, ctx->stream, d, n, sp,     \
                            bank->offset, bank->k0, bank->k_lo, bank->k_hi, bank->rho2_scale, bank->chisq_edges,    \
                            trig, bank->n_tmpl, seg_t0,                                                           \
-                           tps, rho_min, twlo, twhi, chisq_out, trig_out, bad);                                   \
+                           tps, rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad);                         \
         break;
     switch (p) {
         HS_CQ(2) HS_CQ(4) HS_CQ(8) HS_CQ(16)
@@ -132,7 +136,7 @@ using namespace hs;
 
 extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
                         const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
-                        float rho_min, float *chisq_out, hs_trigger *trig_out) {
+                        float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out) {
     HS_REQUIRE(ctx && bank, "hs_chisq: null argument");
     HS_REQUIRE(n_trig >= 0 && n_trig < (int64_t(1) << 31), "hs_chisq: bad trigger count");
     if (n_trig == 0) return HS_OK;
@@ -155,15 +159,15 @@ extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, con
     switch (bank->dtype) {
     case HS_F32:
         HS_TRY(launch_chisq<StoreF32>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                      rho_min, twlo, twhi, chisq_out, trig_out, bad));
+                                      rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
         break;
     case HS_BF16:
         HS_TRY(launch_chisq<StoreBF16>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                       rho_min, twlo, twhi, chisq_out, trig_out, bad));
+                                       rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
         break;
     case HS_F16:
         HS_TRY(launch_chisq<StoreF16>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                      rho_min, twlo, twhi, chisq_out, trig_out, bad));
+                                      rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
         break;
     default: return set_error(HS_EINVAL, "hs_chisq: bad bank dtype");
     }

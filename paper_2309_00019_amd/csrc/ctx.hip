@@ -326,7 +326,7 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 2; }
+int hs_abi_version(void) { return 3; }
 
 int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     if (!ctx) return hs::set_error(HS_EINVAL, "hs_create: ctx is NULL");

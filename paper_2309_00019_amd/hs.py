@@ -25,7 +25,10 @@ COINC = np.dtype([("slide", "<i4"), ("tmpl", "<i4"), ("tick_h", "<i8"), ("tick_l
                   ("snr_h", "<f4"), ("snr_l", "<f4"), ("stat", "<f4"), ("snr_c", "<f4")])
 EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_welch_psd", "hs_whiten",
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
-           "hs_chisq", "hs_timeslide_coinc", "hs_followup"]
+           "hs_chisq", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
+           "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells"]
+MLP_FEATURES, MLP_CELLS, MLP_PARAMS = 16, 64, 43456
+MLP_MODEL = 32 + MLP_PARAMS
 
 
 class HsError(RuntimeError):
@@ -65,10 +68,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_matched_filter": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
         "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
         "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
-        "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P],
+        "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
         "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, P, I32, P, P, I64,
                                ctypes.POINTER(I64)],
         "hs_followup": [P, P, I64, F, P, I32, P, I32, D, I64, I32, P, P],
+        "hs_proposer_features": [P, P, I64, P, I64, P, P, P, I64, P, P, I32, I64, P, P, I32, I64, I64, I64, P],
+        "hs_mlp_forward": [P, P, P, I64, P],
+        "hs_mlp_train_step": [P, P, P, P, I64, F, P, P, I64, P, ctypes.POINTER(F)],
+        "hs_mlp_propose": [P, P, P, I64, F, P],
+        "hs_followup_cells": [P, P, I64, F, P, I32, P, P, I32, D, P, P, I64, I32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -289,17 +297,19 @@ def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: 
 
 
 def hs_chisq(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, trig, seg_t0: int = 0,
-             ticks_per_sample: int = 1, rho_min: float = 0.0, out=None):
-    """Returns (float32 [n_trig] chi2_r, int32 [n_trig, 6] triggers with snr re-weighted by Eq. (4))."""
+             ticks_per_sample: int = 1, rho_min: float = 0.0, out=None, bins: bool = False):
+    """Returns (float32 [n_trig] chi2_r, int32 [n_trig, 6] triggers with snr re-weighted by Eq. (4))
+    and, with bins=True, a third item: float32 [n_trig, p] per-bin chi-square terms."""
     _dev(spec, torch.complex64, "spec")
     _dev(trig, torch.int32, "trig")
     n_trig = trig.shape[0]
     chi = torch.empty(n_trig, dtype=torch.float32, device=trig.device)
     out = torch.empty_like(trig) if out is None else out
+    b = torch.empty((n_trig, max(1, bank.chisq_bins)), dtype=torch.float32, device=trig.device) if bins else None
     bs = bank.struct()
     _check(_lib.hs_chisq(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(trig), n_trig, seg_t0,
-                         ticks_per_sample, float(rho_min), _ptr(chi), _ptr(out)), "hs_chisq")
-    return chi, out
+                         ticks_per_sample, float(rho_min), _ptr(chi), _ptr(out), _ptr(b)), "hs_chisq")
+    return (chi, out, b) if bins else (chi, out)
 
 
 def hs_timeslide_coinc(ctx: Context, trig_h, trig_l, n_tmpl: int, n_slides: int, step: int, window: int,
@@ -337,6 +347,78 @@ def hs_followup(ctx: Context, coincs, rho_min: float, coarse_mchirp, fine_mchirp
     _check(_lib.hs_followup(ctx.handle, _ptr(coincs), coincs.shape[0], float(rho_min), _ptr(coarse_mchirp),
                             coarse_mchirp.numel(), _ptr(fine_mchirp), n_fine, float(frac), seg_ticks, n_seg,
                             _ptr(ids), _ptr(counts)), "hs_followup")
+    return ids, counts.tolist()
+
+
+def hs_proposer_features(ctx: Context, coincs, trig_h, chisq_h, bins_h, trig_l, chisq_l, bins_l, seg_ticks: int,
+                         coarse_mchirp, coarse_q, step: int, wrap: int, ticks_per_second: int, out=None):
+    """float32 [n_c, 16] features of the coincidences (see hs.h)."""
+    _dev(coincs, torch.int32, "coincs")
+    for t, nm in ((trig_h, "trig_h"), (trig_l, "trig_l")):
+        _dev(t, torch.int32, nm)
+    for t, nm in ((chisq_h, "chisq_h"), (chisq_l, "chisq_l"), (bins_h, "bins_h"), (bins_l, "bins_l")):
+        _dev(t, torch.float32, nm)
+    _dev(coarse_mchirp, torch.float64, "coarse_mchirp")
+    _dev(coarse_q, torch.float64, "coarse_q")
+    n_c = coincs.shape[0]
+    out = torch.empty((n_c, MLP_FEATURES), dtype=torch.float32, device=coincs.device) if out is None else out
+    p = bins_h.shape[1] if bins_h.dim() == 2 else 0
+    _check(_lib.hs_proposer_features(ctx.handle, _ptr(coincs), n_c, _ptr(trig_h), trig_h.shape[0], _ptr(chisq_h),
+                                     _ptr(bins_h), _ptr(trig_l), trig_l.shape[0], _ptr(chisq_l), _ptr(bins_l), p,
+                                     seg_ticks, _ptr(coarse_mchirp), _ptr(coarse_q), coarse_mchirp.numel(), step,
+                                     wrap, ticks_per_second, _ptr(out)), "hs_proposer_features")
+    return out
+
+
+def hs_mlp_forward(ctx: Context, model, x, out=None):
+    _dev(model, torch.float32, "model")
+    _dev(x, torch.float32, "x")
+    out = torch.empty((x.shape[0], MLP_CELLS), dtype=torch.float32, device=x.device) if out is None else out
+    _check(_lib.hs_mlp_forward(ctx.handle, _ptr(model), _ptr(x), x.shape[0], _ptr(out)), "hs_mlp_forward")
+    return out
+
+
+def hs_mlp_train_step(ctx: Context, model, adam_m, adam_v, t: int, lr: float, x, labels, grad_out=None) -> float:
+    """One Adam step of the softmax cross-entropy; updates model, adam_m, adam_v in place and
+    returns the batch loss before the update."""
+    _dev(model, torch.float32, "model")
+    _dev(adam_m, torch.float32, "adam_m")
+    _dev(adam_v, torch.float32, "adam_v")
+    _dev(x, torch.float32, "x")
+    _dev(labels, torch.int32, "labels")
+    loss = ctypes.c_float(0.0)
+    _check(_lib.hs_mlp_train_step(ctx.handle, _ptr(model), _ptr(adam_m), _ptr(adam_v), int(t), float(lr), _ptr(x),
+                                  _ptr(labels), x.shape[0], _ptr(grad_out), ctypes.byref(loss)), "hs_mlp_train_step")
+    return float(loss.value)
+
+
+def hs_mlp_propose(ctx: Context, model, x, p_cum: float, out=None):
+    """uint64 cell masks [n] (returned as an int64 device tensor with the same bits)."""
+    _dev(model, torch.float32, "model")
+    _dev(x, torch.float32, "x")
+    out = torch.empty(x.shape[0], dtype=torch.int64, device=x.device) if out is None else out
+    _check(_lib.hs_mlp_propose(ctx.handle, _ptr(model), _ptr(x), x.shape[0], float(p_cum), _ptr(out)),
+           "hs_mlp_propose")
+    return out
+
+
+def hs_followup_cells(ctx: Context, coincs, rho_min: float, coarse_mchirp, fine_mchirp, fine_q, frac: float, q_edges,
+                      cell_mask, seg_ticks: int, n_seg: int):
+    """As hs_followup with per-coincidence cell masks (int64 device tensor of uint64 bits)."""
+    _dev(coincs, torch.int32, "coincs")
+    _dev(coarse_mchirp, torch.float64, "coarse_mchirp")
+    _dev(fine_mchirp, torch.float64, "fine_mchirp")
+    _dev(fine_q, torch.float64, "fine_q")
+    _dev(cell_mask, torch.int64, "cell_mask")
+    qe = np.ascontiguousarray(q_edges, dtype=np.float64)
+    if qe.shape != (3,):
+        raise ValueError("q_edges must hold 3 values")
+    n_fine = fine_mchirp.numel()
+    ids = torch.empty((n_seg, n_fine), dtype=torch.int32, device=coincs.device)
+    counts = np.zeros(n_seg, np.int32)
+    _check(_lib.hs_followup_cells(ctx.handle, _ptr(coincs), coincs.shape[0], float(rho_min), _ptr(coarse_mchirp),
+                                  coarse_mchirp.numel(), _ptr(fine_mchirp), _ptr(fine_q), n_fine, float(frac), _ptr(qe),
+                                  _ptr(cell_mask), seg_ticks, n_seg, _ptr(ids), _ptr(counts)), "hs_followup_cells")
     return ids, counts.tolist()
 
 

@@ -20,7 +20,8 @@ from .glitch import sine_gaussian_glitches
 from .inject import injection_strain, injection_params
 from .strain import make_strain
 from .triggers import (TRIGGER_DTYPE, CANDIDATE_DTYPE, COINC_DTYPE,
-                       synthetic_triggers, synthetic_candidates, synthetic_coincs)
+                       synthetic_triggers, synthetic_candidates, synthetic_coincs,
+                       synthetic_coinc_set)
 
 __all__ = [
     "rng", "NOISE", "GLITCH", "INJECT", "BANK", "TRIG",
@@ -28,5 +29,5 @@ __all__ = [
     "bank_by_tau0", "equal_mass_bank", "sine_gaussian_glitches",
     "injection_strain", "injection_params", "make_strain",
     "TRIGGER_DTYPE", "CANDIDATE_DTYPE", "COINC_DTYPE",
-    "synthetic_triggers", "synthetic_candidates", "synthetic_coincs",
+    "synthetic_triggers", "synthetic_candidates", "synthetic_coincs", "synthetic_coinc_set",
 ]

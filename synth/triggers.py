@@ -84,3 +84,44 @@ def synthetic_coincs(gen: np.random.Generator, count: int, n_tmpl: int, wrap_tic
     rec["snr_h"] = np.sqrt(s / 2).astype(np.float32)
     rec["snr_l"] = np.sqrt(s / 2).astype(np.float32)
     return rec
+
+
+def synthetic_coinc_set(gen: np.random.Generator, n_tmpl: int, n_seg: int, seg_ticks: int, n_trig: int,
+                        n_coinc: int, n_slides: int, p: int = 8):
+    """Random H and L trigger lists (sorted by (seg, tmpl, tick)) with per-trigger chi-square
+    values and p bin terms, and coincidence records that each reference one H and one L trigger
+    of the same template (for feature tests).  Returns (trig_h, chisq_h, bins_h, trig_l, chisq_l,
+    bins_l, coincs); the numbers are arbitrary draws, not outputs of any search step."""
+    def trig_list(count):
+        seg = gen.integers(0, n_seg, count)
+        rec = np.zeros(count, TRIGGER_DTYPE)
+        rec["seg"] = seg
+        rec["tmpl"] = gen.integers(0, n_tmpl, count)
+        rec["tick"] = seg * seg_ticks + gen.integers(0, seg_ticks, count)
+        rec = np.unique(rec)          # sorted by (seg, tmpl, tick); duplicates dropped
+        rec["snr"] = gen.uniform(3.5, 15.0, len(rec)).astype(np.float32)
+        rec["phase"] = gen.uniform(-np.pi, np.pi, len(rec)).astype(np.float32)
+        chi = np.where(gen.random(len(rec)) < 0.3, 0.0, gen.gamma(2.0, 0.8, len(rec))).astype(np.float32)
+        bins = (gen.gamma(1.5, 1.2, (len(rec), p)) * (chi[:, None] > 0)).astype(np.float32)
+        return rec, chi, bins
+
+    th, ch, bh = trig_list(n_trig)
+    tl, cl, bl = trig_list(n_trig)
+    co = np.zeros(n_coinc, COINC_DTYPE)
+    k = 0
+    while k < n_coinc:
+        i = int(gen.integers(0, len(th)))
+        js = np.nonzero(tl["tmpl"] == th["tmpl"][i])[0]
+        if len(js) == 0:
+            continue
+        j = int(js[gen.integers(0, len(js))])
+        co[k]["slide"] = gen.integers(0, n_slides + 1)
+        co[k]["tmpl"] = th["tmpl"][i]
+        co[k]["tick_h"] = th["tick"][i]
+        co[k]["tick_l"] = tl["tick"][j]
+        co[k]["snr_h"] = th["snr"][i]
+        co[k]["snr_l"] = tl["snr"][j]
+        co[k]["stat"] = np.float32(gen.uniform(20.0, 200.0))
+        co[k]["snr_c"] = np.float32(gen.uniform(4.5, 14.0))
+        k += 1
+    return th, ch, bh, tl, cl, bl, co

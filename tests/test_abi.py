@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_abi_version_and_error_string_without_gpu():
     from paper_2309_00019_amd import hs
     lib = hs.load_library()
-    assert lib.hs_abi_version() == 2
+    assert lib.hs_abi_version() == 3
     assert isinstance(lib.hs_last_error(), bytes)
 
 
@@ -50,6 +50,24 @@ def test_argument_errors_need_no_gpu():
     assert lib.hs_whiten(None, None, 1024, 1.0, 0.0, None, None) == hs.HS_EINVAL
     assert lib.hs_create(None, 0, None) == hs.HS_EINVAL
     assert b"null" in lib.hs_last_error().lower()
+    assert lib.hs_mlp_forward(None, None, None, 4, None) == hs.HS_EINVAL
+    assert lib.hs_mlp_propose(None, None, None, 4, 0.9, None) == hs.HS_EINVAL
+    assert lib.hs_mlp_train_step(None, None, None, None, 1, 0.01, None, None, 4, None, None) == hs.HS_EINVAL
+    assert lib.hs_proposer_features(None, None, 1, None, 0, None, None, None, 0, None, None, 8, 1, None, None, 1,
+                                    1, 1, 1, None) == hs.HS_EINVAL
+    assert lib.hs_followup_cells(None, None, 0, 7.0, None, 0, None, None, 0, 0.05, None, None, 1, 0, None,
+                                 None) == hs.HS_EINVAL
+
+
+def test_mlp_sizes_match_header():
+    from paper_2309_00019_amd import hs
+    from oracle import proposer
+    src = open(os.path.join(ROOT, "include", "hs.h")).read()
+    vals = {k: v for k, v in re.findall(r"#define (HS_MLP_[A-Z]+) \(?([0-9]+)", src)}
+    assert int(vals["HS_MLP_FEATURES"]) == hs.MLP_FEATURES == proposer.N_FEATURES
+    assert int(vals["HS_MLP_CELLS"]) == hs.MLP_CELLS == proposer.N_CELLS
+    assert int(vals["HS_MLP_PARAMS"]) == hs.MLP_PARAMS == proposer.N_PARAMS
+    assert hs.MLP_MODEL == proposer.N_MODEL
 
 
 def test_record_round_trip_helpers():

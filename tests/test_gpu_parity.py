@@ -332,28 +332,36 @@ def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind):
     spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
     ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
     cand = hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 4.0)
-    tps = 25
-    trig = hs.hs_cluster_triggers(ctx, cand, n, ids, int(fs), seg_t0=1000, ticks_per_sample=tps)
+    tps, t0 = 25, 1000
+    trig = hs.hs_cluster_triggers(ctx, cand, n, ids, int(fs), seg_t0=t0, ticks_per_sample=tps)
     tr = hs.as_records(trig, hs.TRIGGER)
     assert len(tr) > 10 and tr["snr"].max() > 15
-    chi, rw = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=1000, ticks_per_sample=tps, rho_min=5.0)
-    chi = chi.cpu().numpy()
+    chi, rw, bins = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=5.0, bins=True)
+    chi, bins = chi.cpu().numpy(), bins.cpu().numpy()
     rw = hs.as_records(rw, hs.TRIGGER)
     assert np.array_equal(rw["tick"], tr["tick"]) and np.array_equal(rw["tmpl"], tr["tmpl"])
-    worst = 0.0
+    # the oracle's own triggers (filter, cluster, chi-square at its own samples)
+    ids_np = np.arange(bank.n_tmpl)
+    c = oracle.filter_bank(st, psd, n, fs, f_low, bank, ids_np, 4.0)
+    otr = oracle.triggers_from_candidates(c["tpos"], c["m"], c["rho2"], c["phase"], ids_np, int(fs), 0, t0, tps)
+    otr = oracle.pipeline.reweight_triggers(otr, st, psd, n, fs, f_low, bank, 8, 5.0, tps, t0)
+    okey = {(int(a), int(b)): j for j, (a, b) in enumerate(zip(otr["tmpl"], otr["tick"]))}
+    worst, matched = 0.0, 0
     for i in range(len(tr)):
         if tr["snr"][i] < 5.0:
-            assert chi[i] == 0 and rw["snr"][i] == tr["snr"][i]
+            assert chi[i] == 0 and rw["snr"][i] == tr["snr"][i] and np.all(bins[i] == 0)
             continue
-        t = int(tr["tmpl"][i])
-        h = bank.spectrum(t)
-        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
-        sig = oracle.template_sigma(h, psd, n, fs, a, b)
-        m = (int(tr["tick"][i]) - 1000) // tps
-        c_ref = oracle.chisq_at(st, h, psd, n, fs, sig, m, edges[t])[0]
+        j = okey.get((int(tr["tmpl"][i]), int(tr["tick"][i])))
+        if j is None or otr["snr_raw"][j] < 5.0 * (1 + DELTA["f32"]):
+            continue          # a peak the tolerance rule lets differ
+        matched += 1
+        c_ref = otr["chisq"][j]
         assert abs(chi[i] - c_ref) <= 1e-3 * (1.0 + c_ref), (i, chi[i], c_ref)
-        r_ref = oracle.reweighted_snr([float(tr["snr"][i])], [c_ref])[0]
-        worst = max(worst, abs(rw["snr"][i] / r_ref - 1.0))
+        assert np.all(np.abs(bins[i] - otr["bins"][j]) <= 1e-3 * (1.0 + 14.0 * c_ref)), (i, bins[i], otr["bins"][j])
+        assert abs(bins[i].sum() / 14.0 - chi[i]) <= 1e-4 * (1.0 + chi[i])
+        worst = max(worst, abs(rw["snr"][i] / otr["snr"][j] - 1.0))
+    n_ref = int(np.sum(otr["snr_raw"] >= 5.0 * (1 + DELTA["f32"])))
+    assert matched >= 0.95 * n_ref and matched > 3, (matched, n_ref)
     assert worst < 2e-4
     assert np.any(chi > 3.0)  # the glitches are flagged
 
