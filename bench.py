@@ -7,17 +7,18 @@ sine-Gaussian glitches (0.05/s, Q = 9, f0 40-300 Hz, SNR 6-50) and TaylorF2 inje
 (network SNR 6-20); coarse bank 1,500 templates at 512 Hz and fine bank 30,000 templates at
 2048 Hz (chirp mass 1.4-10, q 1-4, uniform in tau0); background from 2,000 slides of 0.1 s,
 coincidence window 15 ms.  The timed segment pair holds noise and glitches only (the typical
-segment); the missed-injection fractions come from separate one-injection realisations,
-searched by both pipelines outside the timed region.
+segment); the missed-injection fractions come from separate realisations with several
+injections each, searched by every pipeline outside the timed region.
 
 One timed step = the whole hot path on that input with everything resident in HBM:
 Welch PSD + whitening of both detectors, stage 1 (coarse bank at 512 Hz, threshold 3.5),
-trigger clustering, stage-1 coincidence (zero lag + 16 slides of 15 s), follow-up (network
-SNR >= 7, +-5 % chirp-mass neighbourhoods), stage 2 (neighbourhood union at 2048 Hz,
-threshold 4), clustering, chi-square re-weighting (Eq. (4)) of triggers with SNR >= 5.5 at
-both stages, and the 2,000-slide coincidence with background counts.
-The plain flat search (every fine template on both detectors) is timed the same way as the
-comparator.  Prints ONE JSON line on stdout; progress goes to stderr.
+trigger clustering, chi-square re-weighting (Eq. (4)) of triggers with SNR >= 5.5, stage-1
+coincidence (zero lag + 16 slides of 15 s), the learned proposer (features, MLP, cell
+selection) and the follow-up of coincidences with network SNR >= 7, stage 2 (the selected
+neighbourhood cells at 2048 Hz, threshold 4), clustering, re-weighting, and the 2,000-slide
+coincidence with background counts.  The same hierarchy with the plain +-5 % chirp-mass
+neighbourhoods and the flat search (every fine template on both detectors) are timed the same
+way as comparators.  Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -44,42 +45,18 @@ def parse():
     ap.add_argument("--coarse", type=int, default=1500)
     ap.add_argument("--seconds", type=int, default=256)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--injections", type=int, default=64,
-                    help="one-injection realisations for the missed-injection fractions (untimed)")
+    ap.add_argument("--injections", type=int, default=48,
+                    help="realisations for the missed-injection fractions (untimed)")
+    ap.add_argument("--per-seg", type=int, default=6, help="injections per realisation")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--chunk", type=int, default=2048, help="templates generated per host chunk")
     ap.add_argument("--only", choices=["both", "hier", "flat"], default="both",
-                    help="restrict the run (profiling); the JSON line needs the hierarchical path")
+                    help="restrict the run (profiling): hier = hierarchical + proposer only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
-
-
-def make_banks(ctx, hs, synth, n, fs, f_low, m1, m2, psds, dtype, chunk):
-    """Generate TaylorF2 spectra on the host in chunks and prepare one bank per PSD on the device."""
-    import torch
-    from synth.bank import bank_layout
-    k0, kstart, k1, offset, total = bank_layout(m1, m2, n, fs, f_low)
-    banks = [hs.PreparedBank.allocate(n, fs, dtype, offset, k0, total, ctx.device, chisq_bins=8) for _ in psds]
-    T = len(m1)
-    for t0 in range(0, T, chunk):
-        t1 = min(T, t0 + chunk)
-        b = synth.taylorf2_bank(m1[t0:t1], m2[t0:t1], n, fs, f_low)
-        raw = torch.as_tensor(b.data).to(ctx.device)
-        off = torch.as_tensor(b.offset, device=ctx.device)
-        kk0 = torch.as_tensor(b.k0, device=ctx.device)
-        kks = torch.as_tensor(b.kstart, device=ctx.device)
-        kk1 = torch.as_tensor(b.k1, device=ctx.device)
-        for bank, psd in zip(banks, psds):
-            hs.hs_prepare_bank(ctx, n, fs, f_low, psd, raw, off, kk0, kks, kk1, dtype, bank=bank, t0=t0,
-                               elem0=int(offset[t0]))
-        del raw
-    mc = torch.as_tensor(synth.mchirp_eta(m1, m2)[0], device=ctx.device)
-    for bank in banks:
-        bank.mchirp = mc
-    return banks
 
 
 def mf_bytes(units, hs):
@@ -135,7 +112,8 @@ def main():
         sys.exit(2)
     import torch
     import synth
-    from paper_2309_00019_amd import hs, search
+    from paper_2309_00019_amd import hs, search, workload
+    from paper_2309_00019_amd.proposer import Proposer
 
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -146,7 +124,7 @@ def main():
         log(json.dumps({"calib_copy_bytes": src.numel() * 4}))
         return
 
-    fs, f_low = 2048.0, 20.0
+    fs, f_low = workload.FS, workload.F_LOW
     n = int(args.seconds * fs)
     T = n / fs
     cfg = search.SearchConfig(fs=fs, f_low=f_low)
@@ -155,10 +133,10 @@ def main():
     t_setup = time.perf_counter()
 
     # ---- inputs -----------------------------------------------------------------------------
-    fm1, fm2 = synth.bank_by_tau0(args.fine, 1.4, 10.0, 1.0, 4.0, synth.rng(2, 0, 0, synth.BANK))
-    cm1, cm2 = synth.bank_by_tau0(args.coarse, 1.4, 10.0, 1.0, 4.0, synth.rng(2, 1, 0, synth.BANK))
+    fm1, fm2 = workload.bank_masses(args.fine, 0)
+    cm1, cm2 = workload.bank_masses(args.coarse, 1)
     # the timed segment pair: noise + glitches, no signal (the typical segment of a search)
-    strains = [synth.make_strain(2, det, 0, n, fs, f_low, glitch_rate=0.05)[0] for det in (0, 1)]
+    strains = workload.background_strains(n)
     strain_h = torch.as_tensor(strains[0], device=dev)
     strain_l = torch.as_tensor(strains[1], device=dev)
     L = int(4 * fs)
@@ -166,13 +144,14 @@ def main():
     psd_h = hs.hs_welch_psd(ctx, strain_h, fs, L)
     psd_l = hs.hs_welch_psd(ctx, strain_l, fs, L)
     log(f"[setup] generating and preparing {args.fine} fine + {args.coarse} coarse templates ({args.dtype})")
-    fine_h, fine_l = make_banks(ctx, hs, synth, n, fs, f_low, fm1, fm2, [psd_h, psd_l], args.dtype, args.chunk)
+    fine_h, fine_l = workload.make_banks(ctx, n, fs, f_low, fm1, fm2, [psd_h, psd_l], args.dtype, args.chunk)
     n1, fs1 = n // cfg.decim, fs / cfg.decim
-    coarse_h, coarse_l = make_banks(ctx, hs, synth, n1, fs1, f_low, cm1, cm2,
-                                    [psd_h[: n1 // 2 + 1].contiguous(), psd_l[: n1 // 2 + 1].contiguous()],
-                                    args.dtype, args.chunk)
+    coarse_h, coarse_l = workload.make_banks(ctx, n1, fs1, f_low, cm1, cm2,
+                                             [psd_h[: n1 // 2 + 1].contiguous(), psd_l[: n1 // 2 + 1].contiguous()],
+                                             args.dtype, args.chunk)
+    prop = Proposer.load(dev)
     torch.cuda.synchronize()
-    log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s")
+    log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s; proposer P = {prop.p_cum}")
 
     def whiten_both():
         ph = hs.hs_welch_psd(ctx, strain_h, fs, L)
@@ -180,6 +159,11 @@ def main():
         sh = hs.hs_whiten(ctx, strain_h, fs, f_low, ph)
         sl = hs.hs_whiten(ctx, strain_l, fs, f_low, pl)
         return sh[None], sl[None]
+
+    def step_mlp(timed=False):
+        sh, sl = whiten_both()
+        return search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg, time_mf=timed,
+                                          proposer=prop)
 
     def step_hier(timed=False):
         sh, sl = whiten_both()
@@ -202,31 +186,26 @@ def main():
         wall = (time.perf_counter() - t0) / args.steps
         return wall, res
 
-    def injection_campaign(count):
-        """Independent 256 s realisations with one injection each (network SNR 6-20); both
-        searches run on each; an injection is found by a zero-lag coincidence within 0.1 s of
-        its H arrival with network SNR >= 8."""
+    def injection_campaign(count, per_seg):
+        """Independent 256 s realisations with ``per_seg`` injections each (network SNR 6-20);
+        every pipeline runs on each; an injection is found by a zero-lag coincidence within 0.1 s
+        of its H arrival with network SNR >= 8."""
         tick = cfg.ticks_per_second
-        found = {"flat": 0, "hier": 0}
-        followed = []
+        found = {"flat": 0, "hier": 0, "mlp": 0}
+        followed = {"hier": [], "mlp": []}
         for r in range(count):
-            g = synth.rng(2, 0, 100 + r, synth.INJECT)
-            ip = synth.injection_params(1, g, 1.4, 10.0, 1.0, 4.0, T, margin=8.0)
-            specs = []
-            for det, key in ((0, "h"), (1, "l")):
-                inj = dict(m1=ip["m1"][0], m2=ip["m2"][0], t_c=ip["tc_" + key][0], phi_c=ip["phi_" + key][0],
-                           snr=ip["snr_" + key][0])
-                s_, _ = synth.make_strain(2, det, 100 + r, n, fs, f_low, glitch_rate=0.05, injections=[inj])
-                psd = psd_h if det == 0 else psd_l
-                specs.append(hs.hs_whiten(ctx, torch.as_tensor(s_, device=dev), fs, f_low, psd)[None])
-            t_inj = np.array([int(round(ip["tc_h"][0] * tick))])
-            rh = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l, cfg)
-            found["hier"] += found_injections(hs.as_records(rh.coincs, hs.COINC), t_inj, int(0.1 * tick))
-            followed.append(int(sum(rh.followed)))
+            sh_, sl_, ip = workload.injection_realisation(100 + r, n, per_seg)
+            specs = [hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, p)[None]
+                     for x, p in ((sh_, psd_h), (sl_, psd_l))]
+            t_inj = np.round(np.asarray(ip["tc_h"]) * tick).astype(np.int64)
+            for key, kw in (("hier", {}), ("mlp", {"proposer": prop})):
+                res = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l, cfg, **kw)
+                found[key] += found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick))
+                followed[key].append(int(sum(res.followed)))
             if not args.no_flat:
                 rf = search.flat_search(ctx, specs[0], specs[1], fine_h, fine_l, cfg)
                 found["flat"] += found_injections(hs.as_records(rf.coincs, hs.COINC), t_inj, int(0.1 * tick))
-            if (r + 1) % 16 == 0:
+            if (r + 1) % 8 == 0:
                 log(f"[injections] {r + 1}/{count} realisations done")
         return found, followed
 
@@ -236,11 +215,12 @@ def main():
         log(json.dumps({"flat_ms_per_step": wall_f * 1e3, "mf_ms": res_ft.mf_ms, "mf_calls": res_ft.mf_calls}))
         ctx.close()
         return
-    wall_h, res_h = timed(step_hier, "hier")
-    # a separate pass with per-call events around every matched-filter call
-    res_ht = step_hier(timed=True)
+    wall_m, res_m = timed(step_mlp, "hier+mlp")
+    res_mt = step_mlp(timed=True)
+    wall_h = res_h = None
+    if args.only == "both":
+        wall_h, res_h = timed(step_hier, "hier")
     torch.cuda.synchronize()
-    out = {}
     flat = None
     if not args.no_flat and args.only == "both":
         wall_f, res_f = timed(step_flat, "flat")
@@ -248,13 +228,13 @@ def main():
         flat = dict(wall=wall_f, res=res_f, res_t=res_ft)
 
     full_ts = 2 * args.fine * T                      # flat-equivalent template-seconds per step
-    value = full_ts / wall_h
-    raw_ts = res_h.template_seconds + res_h.stage1_template_seconds / cfg.decim
+    value = full_ts / wall_m
+    raw_ts = res_m.template_seconds + res_m.stage1_template_seconds / cfg.decim
 
     # roofline of the matched filter: one "launch" = mf_pass_a + mf_pass_b over one batch of
     # templates; device time from events around every matched-filter call of the event-timed
-    # flat pass (the stage-2 calls of the hierarchical pass when the flat search is skipped)
-    src = flat["res_t"] if flat else res_ht
+    # flat pass (the calls of the hierarchical pass when the flat search is skipped)
+    src = flat["res_t"] if flat else res_mt
     mf_b = mf_bytes(src.mf_units, hs)
     launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel())) for n_, ids, _ in src.mf_units)
     achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
@@ -270,36 +250,46 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall_h * 1e3, 3),
+        "ms_per_step": round(wall_m * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f16": "f16-storage/f32"}[args.dtype],
         "data": "synthetic",
-        "config": {"workload": "two-detector hierarchical search, 2 x %d s at 2048 Hz (noise + glitches 0.05/s), "
-                               "coarse %d @ 512 Hz, fine %d @ 2048 Hz, %d slides x 0.1 s, 15 ms window; "
-                               "missed injections from %d one-injection realisations"
-                               % (args.seconds, args.coarse, args.fine, cfg.n_slides, args.injections),
+        "config": {"workload": "two-detector hierarchical search with the learned follow-up proposer, 2 x %d s at "
+                               "2048 Hz (noise + glitches 0.05/s), coarse %d @ 512 Hz, fine %d @ 2048 Hz, %d slides "
+                               "x 0.1 s, 15 ms window; missed injections from %d realisations x %d injections"
+                               % (args.seconds, args.coarse, args.fine, cfg.n_slides, args.injections, args.per_seg),
                    "fine_templates": args.fine, "coarse_templates": args.coarse, "seconds": args.seconds,
                    "value_definition": "flat-equivalent: fine templates x detectors x seconds / wall per step",
-                   "followed_templates": [int(c) for c in res_h.followed],
-                   "raw_template_seconds_per_s": round(raw_ts / wall_h, 1)},
+                   "followed_templates": [int(c) for c in res_m.followed],
+                   "proposer_p_cum": prop.p_cum,
+                   "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }
+    if res_h is not None:
+        out["hier_plain"] = {"value": round(full_ts / wall_h, 1), "ms_per_step": round(wall_h * 1e3, 3),
+                             "followed_templates": [int(c) for c in res_h.followed]}
     if flat:
         out["flat"] = {"value": round(flat["res"].template_seconds / flat["wall"], 1),
                        "ms_per_step": round(flat["wall"] * 1e3, 3)}
-        out["speedup_vs_flat"] = round(flat["wall"] / wall_h, 3)
+        out["speedup_vs_flat"] = round(flat["wall"] / wall_m, 3)
+        if wall_h:
+            out["speedup_plain_hier_vs_flat"] = round(flat["wall"] / wall_h, 3)
     if args.injections > 0:
-        log(f"[injections] {args.injections} realisations (untimed)")
-        found, followed_inj = injection_campaign(args.injections)
-        inj_out = {"n": args.injections, "found_hier": found["hier"],
-                   "missed_hier": round(1 - found["hier"] / args.injections, 4),
-                   "followed_templates_mean": round(float(np.mean(followed_inj)), 1)}
+        n_inj = args.injections * args.per_seg
+        log(f"[injections] {args.injections} realisations x {args.per_seg} (untimed)")
+        found, followed = injection_campaign(args.injections, args.per_seg)
+        inj_out = {"n": n_inj, "found_mlp": found["mlp"], "found_hier": found["hier"],
+                   "missed_mlp": round(1 - found["mlp"] / n_inj, 4),
+                   "missed_hier": round(1 - found["hier"] / n_inj, 4),
+                   "followed_templates_mean_mlp": round(float(np.mean(followed["mlp"])), 1),
+                   "followed_templates_mean_hier": round(float(np.mean(followed["hier"])), 1)}
         if not args.no_flat:
             inj_out["found_flat"] = found["flat"]
-            inj_out["missed_flat"] = round(1 - found["flat"] / args.injections, 4)
-            inj_out["extra_missed_fraction"] = round((found["flat"] - found["hier"]) / args.injections, 4)
+            inj_out["missed_flat"] = round(1 - found["flat"] / n_inj, 4)
+            inj_out["extra_missed_fraction"] = round((found["flat"] - found["mlp"]) / n_inj, 4)
+            inj_out["extra_missed_fraction_plain_hier"] = round((found["flat"] - found["hier"]) / n_inj, 4)
         out["injections"] = inj_out
     if not args.no_cpu:
         log("[cpu] timing the oracle on a bounded sample")

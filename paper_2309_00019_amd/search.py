@@ -10,7 +10,9 @@ Hierarchical (Sec. III): stage 1 filters the leading quarter of the same whitene
 (ideal decimation to fs/4, same df) with the coarse bank at threshold 3.5, coincides over
 zero lag plus N_sh1 long slides, follows every coincidence with network SNR >= rho1 into the
 union of fine-bank chirp-mass neighbourhoods of its segments, filters those templates at the
-full rate (threshold 4) and coincides over the K background slides.
+full rate (threshold 4) and coincides over the K background slides.  With the learned
+proposer, each followed neighbourhood is cut down to the cells an MLP selects from features of
+the stage-1 coincidence.
 
 Time is int64 ticks of 1/ticks_per_second s; sample m of segment s has tick
 s * seg_ticks + m * ticks_per_sample.
@@ -91,12 +93,15 @@ def whiten_all(ctx, strains, psds, cfg: SearchConfig):
     return out
 
 
-def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None):
-    """Filter + cluster every segment of one detector; returns concatenated trigger records."""
+def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None, with_chisq=False):
+    """Filter + cluster every segment of one detector; returns concatenated trigger records, and
+    with ``with_chisq`` also the chi2_r values and per-bin chi-square terms of those triggers."""
     tps = int(round(cfg.ticks_per_second / fs))
     seg_ticks = specs.shape[1] * 2 * int(round(cfg.ticks_per_second / cfg.fs))
     window = int(round(cfg.window_sec * fs))
-    parts = []
+    parts, chis, bins = [], [], []
+    p = max(1, bank.chisq_bins)
+    use_chisq = cfg.chisq_rho_min is not None and bank.chisq_bins
     for s in range(specs.shape[0]):
         ids = ids_per_seg[s]
         if ids.numel() == 0:
@@ -104,14 +109,22 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
         f = lambda: hs.hs_matched_filter(ctx, specs[s], n, fs, bank, ids, thr)
         cand = timer.run(f, n, ids, bank) if timer else f()
         trig = hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks, ticks_per_sample=tps)
-        if cfg.chisq_rho_min is not None and bank.chisq_bins:
+        if use_chisq:
             # Eq. (4): the coincidence statistic combines re-weighted SNRs
-            _, trig = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
-                                  rho_min=cfg.chisq_rho_min, out=trig)
+            r = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
+                            rho_min=cfg.chisq_rho_min, out=trig, bins=with_chisq)
+            if with_chisq:
+                chis.append(r[0])
+                bins.append(r[2])
+        elif with_chisq:
+            chis.append(torch.zeros(trig.shape[0], dtype=torch.float32, device=specs.device))
+            bins.append(torch.zeros((trig.shape[0], p), dtype=torch.float32, device=specs.device))
         parts.append(trig)
-    if not parts:
-        return torch.zeros((0, 6), dtype=torch.int32, device=specs.device)
-    return torch.cat(parts) if len(parts) > 1 else parts[0]
+    cat = lambda xs, shape: torch.cat(xs) if xs else torch.zeros(shape, dtype=torch.float32, device=specs.device)
+    trig = torch.cat(parts) if parts else torch.zeros((0, 6), dtype=torch.int32, device=specs.device)
+    if not with_chisq:
+        return trig
+    return trig, cat(chis, (0,)), cat(bins, (0, p))
 
 
 def _coinc(ctx, th, tl, n_tmpl, n_slides, step_sec, cfg, wrap, edges):
@@ -138,23 +151,53 @@ def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=
                         mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units)
 
 
+def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=None, with_chisq=False):
+    """Stage 1 of Sec. III: the coarse bank on the leading quarter of each whitened spectrum
+    (ideal decimation to fs / decim, same df), threshold thr1, coincidence over zero lag and
+    n_sh1 slides of t_sh1.  Returns (trig_h, trig_l, coincs) where with ``with_chisq`` each
+    trigger entry is (records, chi2_r, per-bin terms)."""
+    n = spec_h.shape[1] * 2
+    n1, fs1 = n // cfg.decim, cfg.fs / cfg.decim
+    n_seg = spec_h.shape[0]
+    c_ids = torch.arange(coarse_h.n_tmpl, dtype=torch.int32, device=spec_h.device)
+    th = detector_triggers(ctx, spec_h, n1, fs1, coarse_h, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq)
+    tl = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq)
+    wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
+    c1, _ = _coinc(ctx, th[0] if with_chisq else th, tl[0] if with_chisq else tl, coarse_h.n_tmpl, cfg.n_sh1,
+                   cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32))
+    return th, tl, c1
+
+
+def stage1_features(ctx, th, tl, c1, coarse, n_seg: int, n: int, cfg: SearchConfig):
+    """Proposer features of the stage-1 coincidences (th / tl as returned by stage1 with chisq)."""
+    tpt = int(round(cfg.ticks_per_second / cfg.fs))
+    seg_ticks = n * tpt
+    return hs.hs_proposer_features(ctx, c1, th[0], th[1], th[2], tl[0], tl[1], tl[2], seg_ticks, coarse.mchirp,
+                                   coarse.q, int(round(cfg.t_sh1_sec * cfg.ticks_per_second)), n_seg * seg_ticks,
+                                   cfg.ticks_per_second)
+
+
 def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l, cfg: SearchConfig,
-                        time_mf=False) -> SearchResult:
-    """Two-stage search; each bank is given per detector (prepared with that detector's PSD)."""
+                        time_mf=False, proposer=None) -> SearchResult:
+    """Two-stage search; each bank is given per detector (prepared with that detector's PSD).
+    With a ``proposer`` (paper_2309_00019_amd.proposer.Proposer) the follow-up keeps only the
+    neighbourhood cells the learned proposer selects; the banks then need ``q`` (m1 / m2)."""
     coarse, fine = coarse_h, fine_h
     n = spec_h.shape[1] * 2
     n_seg = spec_h.shape[0]
-    n1, fs1 = n // cfg.decim, cfg.fs / cfg.decim
-    dev = spec_h.device
     timer = _MFTimer(ctx, time_mf)
-    c_ids = torch.arange(coarse.n_tmpl, dtype=torch.int32, device=dev)
-    t1h = detector_triggers(ctx, spec_h, n1, fs1, coarse_h, [c_ids] * n_seg, cfg.thr1, cfg, timer)
-    t1l = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer)
     tpt = int(round(cfg.ticks_per_second / cfg.fs))
     seg_ticks = n * tpt
     wrap = n_seg * seg_ticks
-    c1, _ = _coinc(ctx, t1h, t1l, coarse.n_tmpl, cfg.n_sh1, cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32))
-    ids2, counts = hs.hs_followup(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, cfg.mc_frac, seg_ticks, n_seg)
+    use_p = proposer is not None
+    t1h, t1l, c1 = stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg, timer, with_chisq=use_p)
+    if use_p:
+        feats = stage1_features(ctx, t1h, t1l, c1, coarse, n_seg, n, cfg)
+        masks = hs.hs_mlp_propose(ctx, proposer.model, feats, proposer.p_cum)
+        ids2, counts = hs.hs_followup_cells(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, fine.q, cfg.mc_frac,
+                                            proposer.q_edges, masks, seg_ticks, n_seg)
+    else:
+        ids2, counts = hs.hs_followup(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, cfg.mc_frac, seg_ticks, n_seg)
     per_seg = [ids2[s, :counts[s]] for s in range(n_seg)]
     th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, per_seg, cfg.thr2, cfg, timer)
     tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, per_seg, cfg.thr2, cfg, timer)

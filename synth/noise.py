@@ -16,6 +16,13 @@ from .psd import aligo_psd_fit
 def coloured_noise(n: int, fs: float, gen: np.random.Generator, f_min: float,
                    psd_fn=aligo_psd_fit) -> np.ndarray:
     """Return float64 noise of length ``n`` sampled at ``fs`` Hz."""
+    # numpy's irfft carries a 1/N; multiplying by N*df = fs undoes it and applies df.
+    return np.fft.irfft(coloured_noise_spectrum(n, fs, gen, f_min, psd_fn), n=n) * fs
+
+
+def coloured_noise_spectrum(n: int, fs: float, gen: np.random.Generator, f_min: float,
+                            psd_fn=aligo_psd_fit) -> np.ndarray:
+    """The one-sided spectrum n~_k (k = 0..n/2, complex128) of ``coloured_noise``."""
     df = fs / n
     k = np.arange(n // 2 + 1)
     f = k * df
@@ -25,5 +32,4 @@ def coloured_noise(n: int, fs: float, gen: np.random.Generator, f_min: float,
     x = gen.standard_normal(sel.sum())
     y = gen.standard_normal(sel.sum())
     spec[sel] = amp * (x + 1j * y)
-    # numpy's irfft carries a 1/N; multiplying by N*df = fs undoes it and applies df.
-    return np.fft.irfft(spec, n=n) * fs
+    return spec

@@ -2,9 +2,9 @@
 import numpy as np
 
 from .seeds import rng, NOISE, GLITCH
-from .noise import coloured_noise
+from .noise import coloured_noise_spectrum
 from .glitch import sine_gaussian_glitches
-from .inject import injection_strain
+from .inject import injection_spectrum
 from .psd import aligo_psd_fit
 
 
@@ -14,17 +14,23 @@ def make_strain(cfg: int, det: int, seg: int, n: int, fs: float, f_low: float,
     """Return (float32 strain [n], info dict).
 
     ``injections`` is a sequence of dicts with keys m1, m2, t_c, phi_c, snr.
-    Noise is high-passed at 0.75 f_low.
+    Noise is high-passed at 0.75 f_low.  Noise and injections are summed in the frequency
+    domain and transformed once; glitches are added in the time domain.
     """
-    s = np.zeros(n, dtype=np.float64)
+    spec = np.zeros(n // 2 + 1, dtype=np.complex128)
     if noise:
-        s += coloured_noise(n, fs, rng(cfg, det, seg, NOISE), 0.75 * f_low, psd_fn)
+        spec += coloured_noise_spectrum(n, fs, rng(cfg, det, seg, NOISE), 0.75 * f_low, psd_fn)
+    if len(injections):
+        grid = np.empty(n // 2 + 1)
+        grid[1:] = psd_fn(np.arange(1, n // 2 + 1) * (fs / n))
+        grid[0] = grid[1]
+        for inj in injections:
+            spec += injection_spectrum(n, fs, f_low, inj["m1"], inj["m2"], inj["t_c"], inj["phi_c"],
+                                       inj["snr"], psd_fn, grid)
+    s = np.fft.irfft(spec, n=n) * fs
     glitches = []
     if glitch_rate > 0:
         g, glitches = sine_gaussian_glitches(n, fs, rng(cfg, det, seg, GLITCH), glitch_rate,
                                              psd_fn=psd_fn)
         s += g
-    for inj in injections:
-        s += injection_strain(n, fs, f_low, inj["m1"], inj["m2"], inj["t_c"], inj["phi_c"],
-                              inj["snr"], psd_fn)
     return s.astype(np.float32), dict(glitches=glitches)
