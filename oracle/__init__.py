@@ -21,6 +21,7 @@ NumPy/SciPy, citing the passage of the paper it follows:
 * ``chisq``     -- power-consistency chi-square, its per-bin terms, re-weighted SNR (Eq. (4))
 * ``proposer``  -- learned follow-up proposer: coincidence features, MLP forward/backward,
                    Adam, cell selection and the cell-restricted neighbourhood rule
+* ``farfit``    -- background tail fit and extrapolated FAR (Sec. IV, Eqs. (6)-(7))
 
 Where the paper is silent or garbled the reading taken is stated in the
 docstring of the function that takes it.
@@ -42,5 +43,6 @@ __all__ = [
 ]
 from .chisq import chisq_bin_edges, chisq_at, bin_snrs, chisq_terms, reweighted_snr  # noqa: E402
 from . import proposer  # noqa: E402
+from . import farfit  # noqa: E402
 
-__all__ += ["chisq_bin_edges", "chisq_at", "bin_snrs", "chisq_terms", "reweighted_snr", "proposer"]
+__all__ += ["chisq_bin_edges", "chisq_at", "bin_snrs", "chisq_terms", "reweighted_snr", "proposer", "farfit"]
