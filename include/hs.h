@@ -253,6 +253,32 @@ int hs_followup(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_min,
                 int32_t n_fine, double frac, int64_t seg_ticks, int32_t n_seg, int32_t *fine_ids,
                 int32_t *n_ids);
 
+/*
+ * Background tail fit of Sec. IV, Eq. (7): ordinary least squares of
+ * log counts[e] = alpha + beta edges[e] over the edges with edges[e] >= x_min
+ * and counts[e] > 0 (counts = the cumulative background counts n_b(edges[e])
+ * of hs_timeslide_coinc; natural logarithm, equal weights, float64).  Host
+ * pointers; no device work.  HS_EINVAL if fewer than two edges qualify.
+ */
+int hs_far_fit(const float *edges, const int64_t *counts, int32_t n_edges, float x_min, double *alpha,
+               double *beta, int32_t *n_used);
+
+/*
+ * Hybrid false-alarm rate (Eq. (6) below the fit range, Eq. (7) above) of every
+ * zero-lag coincidence of c (an hs_timeslide_coinc output: slide 0 = foreground,
+ * slides >= 1 = background survivors).  With rho = sqrt((double)stat):
+ *   rho <  x_fit: far = (1 + #{background records with stat >= this stat}) / t_b
+ *   rho >= x_fit: far = exp(alpha + beta rho) / t_b
+ * (per second when t_b is in seconds); background records get -1.
+ *   c device [n_c]; far_out device double [n_c].
+ */
+int hs_far(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, double t_b, double alpha, double beta, float x_fit,
+           double *far_out);
+
+/* Statistic at which the fitted FAR exp(alpha + beta x) / t_b equals 1 / ifar
+ * (t_b and ifar in the same unit): (log(t_b / ifar) - alpha) / beta. */
+double hs_far_threshold(double alpha, double beta, double t_b, double ifar);
+
 /* ---------------------------------------------------------------------------
  * Learned follow-up proposer (an addition on top of Sec. III's neighbourhood
  * rule).  The neighbourhood of a followed coarse template c (every fine f with

@@ -1,6 +1,7 @@
 """Build libhs.so (all HIP sources for gfx950) in-tree.
 
-Usage: python -m paper_2309_00019_amd.build [--jobs N]
+Usage: python paper_2309_00019_amd/build.py [--jobs N]   (by path: importing the package first
+would load the library being rebuilt)
 """
 import argparse
 import os
@@ -15,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhs.so")
 ARCH = "gfx950"
 
-SOURCES = ["ctx.hip", "whiten.hip", "bank.hip", "mf.hip", "cluster.hip", "chisq.hip", "coinc.hip", "followup.hip", "proposer.hip"]
+SOURCES = ["ctx.hip", "whiten.hip", "bank.hip", "mf.hip", "cluster.hip", "chisq.hip", "coinc.hip", "followup.hip", "proposer.hip", "far.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit (the host pass
 # ignores the feature with a warning).

@@ -26,7 +26,8 @@ COINC = np.dtype([("slide", "<i4"), ("tmpl", "<i4"), ("tick_h", "<i8"), ("tick_l
 EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_welch_psd", "hs_whiten",
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
            "hs_chisq", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
-           "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells"]
+           "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells", "hs_far_fit", "hs_far",
+           "hs_far_threshold"]
 MLP_FEATURES, MLP_CELLS, MLP_PARAMS = 16, 64, 43456
 MLP_MODEL = 32 + MLP_PARAMS
 
@@ -54,7 +55,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"libhs.so not found at {path}: build it with `python -m paper_2309_00019_amd.build`")
+        raise ImportError(f"libhs.so not found at {path}: build it with `python paper_2309_00019_amd/build.py` (or __graft_entry__.build())")
     lib = ctypes.CDLL(path)
     P, I32, I64, D, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
     sig = {
@@ -77,11 +78,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_mlp_train_step": [P, P, P, P, I64, F, P, P, I64, P, ctypes.POINTER(F)],
         "hs_mlp_propose": [P, P, P, I64, F, P],
         "hs_followup_cells": [P, P, I64, F, P, I32, P, P, I32, D, P, P, I64, I32, P, P],
+        "hs_far_fit": [P, P, I32, F, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32)],
+        "hs_far": [P, P, I64, D, D, D, F, P],
+        "hs_far_threshold": [D, D, D, D],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name == "hs_last_error" else ctypes.c_int
+        fn.restype = {"hs_last_error": ctypes.c_char_p, "hs_far_threshold": ctypes.c_double}.get(name, ctypes.c_int)
     _lib = lib
     return lib
 
@@ -420,6 +424,29 @@ def hs_followup_cells(ctx: Context, coincs, rho_min: float, coarse_mchirp, fine_
                                   coarse_mchirp.numel(), _ptr(fine_mchirp), _ptr(fine_q), n_fine, float(frac), _ptr(qe),
                                   _ptr(cell_mask), seg_ticks, n_seg, _ptr(ids), _ptr(counts)), "hs_followup_cells")
     return ids, counts.tolist()
+
+
+def hs_far_fit(edges, counts, x_min: float):
+    """(alpha, beta, n_used) of the Eq. (7) tail fit (host arrays)."""
+    e = np.ascontiguousarray(edges, dtype=np.float32)
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    a, b, m = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(_lib.hs_far_fit(_ptr(e), _ptr(c), len(e), float(x_min), ctypes.byref(a), ctypes.byref(b), ctypes.byref(m)),
+           "hs_far_fit")
+    return a.value, b.value, m.value
+
+
+def hs_far(ctx: Context, coincs, t_b: float, alpha: float, beta: float, x_fit: float, out=None):
+    """float64 [n] hybrid FAR of the zero-lag records (-1 for background records)."""
+    _dev(coincs, torch.int32, "coincs")
+    out = torch.empty(coincs.shape[0], dtype=torch.float64, device=coincs.device) if out is None else out
+    _check(_lib.hs_far(ctx.handle, _ptr(coincs), coincs.shape[0], float(t_b), float(alpha), float(beta), float(x_fit),
+                       _ptr(out)), "hs_far")
+    return out
+
+
+def hs_far_threshold(alpha: float, beta: float, t_b: float, ifar: float) -> float:
+    return float(_lib.hs_far_threshold(float(alpha), float(beta), float(t_b), float(ifar)))
 
 
 def as_records(t, dtype) -> np.ndarray:

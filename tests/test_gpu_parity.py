@@ -388,3 +388,55 @@ def test_exact_capacity_holds_unevenly_spread_candidates(ctx):
     tight = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 3.0, cap=len(full)), hs.CANDIDATE)
     key = lambda r: sorted(zip(r["tpos"].tolist(), r["m"].tolist()))
     assert key(tight) == key(full)
+
+
+# ------------------------------------------------------------------------------------------
+# Background tail fit and hybrid FAR (Sec. IV, Eqs. (6)-(7))
+# ------------------------------------------------------------------------------------------
+def test_far_of_synthetic_records_matches_oracle(ctx):
+    from paper_2309_00019_amd import hs
+    from oracle import farfit as F
+    _say("far synthetic records")
+    g = np.random.default_rng(710)
+    co = synth.synthetic_coincs(g, 5000, 30, 51200 * 256, 51200 * 256, 40, stat=(36.0, 140.0))
+    co = co[np.lexsort((co["tick_h"], co["slide"]))]
+    t_b = 40 * 256.0
+    alpha, beta, x_fit = 15.0, -1.3, 10.5
+    got = hs.hs_far(ctx, hs.to_device_records(co, ctx.device), t_b, alpha, beta, x_fit).cpu().numpy()
+    fg = co["slide"] == 0
+    assert np.all(got[~fg] == -1.0)
+    ref = F.far(co["stat"][fg], co["stat"][~fg], t_b, alpha, beta, x_fit)
+    assert fg.sum() > 50
+    assert np.allclose(got[fg], ref, rtol=1e-13, atol=0)
+    assert np.any(np.sqrt(co["stat"][fg].astype(np.float64)) >= x_fit)     # both branches exercised
+
+
+def test_background_fit_and_far_end_to_end_on_identical_triggers(ctx):
+    from paper_2309_00019_amd import hs
+    from oracle import farfit as F
+    _say("far end to end")
+    g = np.random.default_rng(711)
+    wrap = 51200 * 256
+    th = synth.synthetic_triggers(g, 40, wrap, 160, 25, wrap, snr=(4.0, 7.5))
+    tl = synth.synthetic_triggers(g, 40, wrap, 160, 25, wrap, snr=(4.0, 7.5))
+    edges = np.arange(6.0, 10.6, 0.1, dtype=np.float32)
+    K, step, win, cw = 400, 5120, 768, 51200
+    co, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(th, ctx.device), hs.to_device_records(tl, ctx.device),
+                                   40, K, step, win, wrap, cw, edges)
+    ref = oracle.timeslide_coinc(dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"]),
+                                 dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"]),
+                                 K, step, win, wrap, cw, edges, 51200)
+    assert np.array_equal(bg, ref["bg_counts"])
+    rc = ref["coincs"]
+    assert np.array_equal(F.cumulative_counts(rc["stat"][rc["slide"] >= 1], edges), ref["bg_counts"])
+    a, b, m = hs.hs_far_fit(edges, bg, 7.0)
+    ra, rb, rm = F.tail_fit(edges, ref["bg_counts"], 7.0)
+    assert m == rm and m >= 5 and b < 0
+    assert abs(a - ra) <= 1e-12 * abs(ra) and abs(b - rb) <= 1e-12 * abs(rb)
+    t_b = K * wrap / 51200.0
+    far = hs.hs_far(ctx, co, t_b, a, b, 8.0).cpu().numpy()
+    rec = hs.as_records(co, hs.COINC)
+    fg = rec["slide"] == 0
+    want = F.far(rc["stat"][rc["slide"] == 0], rc["stat"][rc["slide"] >= 1], t_b, ra, rb, 8.0)
+    assert fg.sum() == len(want) and fg.sum() > 0
+    assert np.allclose(far[fg], want, rtol=1e-12, atol=0)
