@@ -116,12 +116,25 @@ def main():
     from paper_2309_00019_amd.proposer import Proposer
 
     if args.calib_copy:
+        # reference kernels of known size: a 1 GiB device copy (calibrates the HBM byte
+        # counters) and the achievable bandwidth of copy and write-only fill
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(json.dumps({"calib_copy_bytes": src.numel() * 4}))
+        rates = {}
+        for name, fn, nbytes in (("copy", lambda: dst.copy_(src), 8 * src.numel()),
+                                 ("fill", lambda: dst.fill_(1.0), 4 * src.numel())):
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(10):
+                fn()
+            e.record()
+            e.synchronize()
+            rates[name + "_GBs"] = round(nbytes * 10 / (s.elapsed_time(e) * 1e-3) / 1e9, 1)
+        log(json.dumps({"calib_copy_bytes": src.numel() * 4, **rates}))
         return
 
     fs, f_low = workload.FS, workload.F_LOW
