@@ -173,18 +173,37 @@ def main():
         sl = hs.hs_whiten(ctx, strain_l, fs, f_low, pl)
         return sh[None], sl[None]
 
+    def with_far(res):
+        res.far = search.background_far(ctx, res, cfg)
+        return res
+
     def step_mlp(timed=False):
         sh, sl = whiten_both()
-        return search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg, time_mf=timed,
-                                          proposer=prop)
+        return with_far(search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg,
+                                                   time_mf=timed, proposer=prop))
 
     def step_hier(timed=False):
         sh, sl = whiten_both()
-        return search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg, time_mf=timed)
+        return with_far(search.hierarchical_search(ctx, sh, sl, coarse_h, coarse_l, fine_h, fine_l, cfg,
+                                                   time_mf=timed))
 
     def step_flat(timed=False):
         sh, sl = whiten_both()
-        return search.flat_search(ctx, sh, sl, fine_h, fine_l, cfg, time_mf=timed)
+        return with_far(search.flat_search(ctx, sh, sl, fine_h, fine_l, cfg, time_mf=timed))
+
+    def far_summary(res):
+        f = res.far
+        if f is None:
+            return None
+        rec = hs.as_records(res.coincs, hs.COINC)
+        far = f["far"].cpu().numpy()
+        fg = rec["slide"] == 0
+        i = int(np.argmax(np.where(fg, rec["snr_c"], -1.0))) if fg.any() else None
+        return {"alpha": round(f["alpha"], 4), "beta": round(f["beta"], 4), "fit_points": f["n_fit"],
+                "background_days": round(f["t_b"] / 86400.0, 2),
+                "rho_c_at_ifar_1yr": round(f["ifar_1yr"], 3), "rho_c_at_ifar_10yr": round(f["ifar_10yr"], 3),
+                "loudest_foreground_rho_c": None if i is None else round(float(rec["snr_c"][i]), 3),
+                "loudest_foreground_far_per_yr": None if i is None else float(far[i] * search.YEAR)}
 
     def timed(step, label):
         for _ in range(args.warmup):
@@ -205,7 +224,18 @@ def main():
         of its H arrival with network SNR >= 8."""
         tick = cfg.ticks_per_second
         found = {"flat": 0, "hier": 0, "mlp": 0}
+        found_1yr = {"flat": 0, "hier": 0, "mlp": 0}
         followed = {"hier": [], "mlp": []}
+
+        def detected_1yr(res, t_inj):
+            """Injections with a zero-lag coincidence within 0.1 s whose hybrid FAR <= 1 / yr."""
+            f = search.background_far(ctx, res, cfg)
+            if f is None:
+                return 0
+            rec = hs.as_records(res.coincs, hs.COINC)
+            far = f["far"].cpu().numpy()
+            ok = (rec["slide"] == 0) & (far >= 0) & (far <= 1.0 / search.YEAR)
+            return int(sum(np.any(np.abs(rec["tick_h"][ok] - t) <= int(0.1 * tick)) for t in t_inj))
         for r in range(count):
             sh_, sl_, ip = workload.injection_realisation(100 + r, n, per_seg)
             specs = [hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, p)[None]
@@ -214,13 +244,15 @@ def main():
             for key, kw in (("hier", {}), ("mlp", {"proposer": prop})):
                 res = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l, cfg, **kw)
                 found[key] += found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick))
+                found_1yr[key] += detected_1yr(res, t_inj)
                 followed[key].append(int(sum(res.followed)))
             if not args.no_flat:
                 rf = search.flat_search(ctx, specs[0], specs[1], fine_h, fine_l, cfg)
                 found["flat"] += found_injections(hs.as_records(rf.coincs, hs.COINC), t_inj, int(0.1 * tick))
+                found_1yr["flat"] += detected_1yr(rf, t_inj)
             if (r + 1) % 8 == 0:
                 log(f"[injections] {r + 1}/{count} realisations done")
-        return found, followed
+        return found, followed, found_1yr
 
     if args.only == "flat":
         wall_f, res_f = timed(step_flat, "flat")
@@ -280,10 +312,12 @@ def main():
                    "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }
+    out["far"] = {"hier_mlp": far_summary(res_m)}
     if res_h is not None:
         out["hier_plain"] = {"value": round(full_ts / wall_h, 1), "ms_per_step": round(wall_h * 1e3, 3),
                              "followed_templates": [int(c) for c in res_h.followed]}
     if flat:
+        out["far"]["flat"] = far_summary(flat["res"])
         out["flat"] = {"value": round(flat["res"].template_seconds / flat["wall"], 1),
                        "ms_per_step": round(flat["wall"] * 1e3, 3)}
         out["speedup_vs_flat"] = round(flat["wall"] / wall_m, 3)
@@ -292,13 +326,18 @@ def main():
     if args.injections > 0:
         n_inj = args.injections * args.per_seg
         log(f"[injections] {args.injections} realisations x {args.per_seg} (untimed)")
-        found, followed = injection_campaign(args.injections, args.per_seg)
+        found, followed, found_1yr = injection_campaign(args.injections, args.per_seg)
         inj_out = {"n": n_inj, "found_mlp": found["mlp"], "found_hier": found["hier"],
                    "missed_mlp": round(1 - found["mlp"] / n_inj, 4),
                    "missed_hier": round(1 - found["hier"] / n_inj, 4),
                    "followed_templates_mean_mlp": round(float(np.mean(followed["mlp"])), 1),
                    "followed_templates_mean_hier": round(float(np.mean(followed["hier"])), 1)}
+        inj_out["detected_ifar_1yr_mlp"] = found_1yr["mlp"]
+        inj_out["detected_ifar_1yr_hier"] = found_1yr["hier"]
         if not args.no_flat:
+            inj_out["detected_ifar_1yr_flat"] = found_1yr["flat"]
+            if found_1yr["flat"]:
+                inj_out["sensitivity_ratio_ifar_1yr_mlp_vs_flat"] = round(found_1yr["mlp"] / found_1yr["flat"], 4)
             inj_out["found_flat"] = found["flat"]
             inj_out["missed_flat"] = round(1 - found["flat"] / n_inj, 4)
             inj_out["extra_missed_fraction"] = round((found["flat"] - found["mlp"]) / n_inj, 4)

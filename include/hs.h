@@ -346,11 +346,13 @@ int hs_mlp_train_step(hs_ctx *ctx, float *model, float *adam_m, float *adam_v, i
 /*
  * Cell selection: per row, softmax of the logits (float32), cells taken in
  * decreasing probability (equal probabilities: lower cell first) until the
- * running sum reaches p_cum (all 64 if it never does).  mask_out device
- * uint64 [n], bit c = cell c selected.
+ * running sum reaches P (all 64 if it never does), where P = p_cum for rows
+ * with x[2] (the network SNR feature) >= rho_split and p_cum_low otherwise
+ * (two tiers; rho_split = -inf gives one).  mask_out device uint64 [n], bit
+ * c = cell c selected.
  */
 int hs_mlp_propose(hs_ctx *ctx, const float *model, const float *x, int64_t n, float p_cum,
-                   uint64_t *mask_out);
+                   float rho_split, float p_cum_low, uint64_t *mask_out);
 
 /*
  * Follow-up restricted to cells: as hs_followup, but a followed coincidence i

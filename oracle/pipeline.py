@@ -101,8 +101,10 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                         n_sh1=16, t_sh1_sec=15.0, rho1=7.0, mc_frac=0.05,
                         n_slides=2000, step_sec=0.1, coinc_window_sec=0.015, cluster_sec=1.0,
                         edges=(8.0,), chisq_bins=8, chisq_rho_min=None, proposer=None):
-    """``proposer`` = (model, q_edges, p_cum) switches the follow-up to the learned cell rule
-    (``proposer`` module); the bank objects then need ``q`` (mass ratio m1/m2 >= 1) as well."""
+    """``proposer`` = (model, q_edges, p_cum[, rho_low, p_cum_low]) switches the follow-up to the
+    learned cell rule (``proposer`` module): coincidences with rho_c >= rho1 keep the cells of
+    cumulative probability p_cum, those with rho_low <= rho_c < rho1 the cells of p_cum_low; the
+    bank objects then need ``q`` (mass ratio m1/m2 >= 1) as well."""
     n_seg = len(h_segments)
     n_full = len(h_segments[0])
     tpt = int(round(ticks_per_second / fs))
@@ -124,12 +126,17 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                                       seg_ticks, n_seg)
     else:
         # learned proposer: cells of each followed neighbourhood ranked by the MLP
-        model, q_edges, p_cum = proposer
+        model, q_edges, p_cum = proposer[:3]
+        rho_low, p_low = proposer[3:5] if len(proposer) >= 5 else (rho1, p_cum)
         cc = c1["coincs"]
         feats = _proposer.features(cc, t1h, t1l, coarse.mchirp, coarse.q, int(round(t_sh1_sec * ticks_per_second)),
                                    wrap, ticks_per_second, chisq_bins)
-        masks = _proposer.select_cells(_proposer.forward(model, feats)[0], p_cum) if len(feats) else np.zeros(0, np.uint64)
-        fine_ids = _proposer.followup_cells(cc, rho1, coarse.mchirp, fine.mchirp, fine.q, q_edges, mc_frac,
+        if len(feats):
+            masks = _proposer.select_cells(_proposer.forward(model, feats)[0], p_cum,
+                                           feats[:, 2].astype(np.float32), rho1, p_low)
+        else:
+            masks = np.zeros(0, np.uint64)
+        fine_ids = _proposer.followup_cells(cc, rho_low, coarse.mchirp, fine.mchirp, fine.q, q_edges, mc_frac,
                                             seg_ticks, n_seg, masks)
     t2h = detector_triggers(h_segments, h_psds, fs, f_low, fine, fine_ids, thr2, window_sec,
                             ticks_per_second, **kw)

@@ -25,6 +25,8 @@ small multilayer perceptron (MLP) ranks as likely to hold the signal:
 * Selection: cells sorted by softmax probability (descending; equal probabilities by lower cell
   index); the smallest leading set whose cumulative probability reaches P is followed (all 64
   cells if the sum never reaches P).  All 64 cells give back the plain neighbourhood rule.
+  Two tiers: coincidences with rho_c >= rho_split use P, weaker ones (followed down to a lower
+  threshold) use a smaller P_low.
 
 Model layout (float32 in the library, float64 here): one flat vector
   [mu (16), inv_std (16), W1 (16 x 128), b1, W2 (128 x 128), b2, W3 (128 x 128), b3, W4 (128 x 64), b4]
@@ -109,17 +111,22 @@ def adam_step(theta, m, v, g, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-
     return np.asarray(theta, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def select_cells(logits, p_cum: float):
-    """uint64 cell masks: smallest set of most probable cells with cumulative probability >= p_cum."""
+def select_cells(logits, p_cum: float, rho_c=None, rho_split: float = None, p_cum_low: float = None):
+    """uint64 cell masks: smallest set of most probable cells with cumulative probability >=
+    p_cum.  Two tiers: with rho_c (float32 feature 2 of each row) and rho_split given, rows with
+    rho_c < rho_split use p_cum_low instead."""
     p = softmax(logits)
     out = np.zeros(len(p), np.uint64)
     for i in range(len(p)):
+        pc = p_cum
+        if rho_split is not None and float(np.float32(rho_c[i])) < float(np.float32(rho_split)):
+            pc = p_cum_low
         order = sorted(range(N_CELLS), key=lambda c: (-p[i, c], c))
         acc, mask = 0.0, 0
         for c in order:
             mask |= 1 << c
             acc += p[i, c]
-            if acc >= p_cum:
+            if acc >= pc:
                 break
         out[i] = np.uint64(mask)
     return out

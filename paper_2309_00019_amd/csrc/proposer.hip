@@ -229,12 +229,15 @@ __global__ void mlp_adam(float *__restrict__ theta, float *__restrict__ m, float
     theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
 }
 
-// Top-probability cell selection: one wavefront per row, lane c holds cell c.
-__global__ __launch_bounds__(256) void mlp_select(const float *__restrict__ logits, int64_t n, float p_cum,
+// Top-probability cell selection: one wavefront per row, lane c holds cell c.  Rows whose
+// feature 2 (the network SNR) is below rho_split use p_cum_low.
+__global__ __launch_bounds__(256) void mlp_select(const float *__restrict__ logits, const float *__restrict__ x,
+                                                  int64_t n, float p_cum, float rho_split, float p_cum_low,
                                                   uint64_t *__restrict__ mask_out) {
     const int64_t i = blockIdx.x * 4ll + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= n) return;  // whole wavefronts leave together
+    const float pc = x[i * MLP_F + 2] >= rho_split ? p_cum : p_cum_low;
     const float z = logits[i * MLP_C + lane];
     float mx = z;
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_down(mx, o));
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(256) void mlp_select(const float *__restrict__ logi
         if (lane == bl) taken = true;
         mask |= 1ull << bl;
         acc += bv;
-        if (acc >= p_cum) break;
+        if (acc >= pc) break;
     }
     if (lane == 0) mask_out[i] = mask;
 }
@@ -397,7 +400,7 @@ extern "C" int hs_mlp_train_step(hs_ctx *ctx, float *model, float *adam_m, float
 }
 
 extern "C" int hs_mlp_propose(hs_ctx *ctx, const float *model, const float *x, int64_t n, float p_cum,
-                              uint64_t *mask_out) {
+                              float rho_split, float p_cum_low, uint64_t *mask_out) {
     HS_REQUIRE(ctx && n >= 0, "hs_mlp_propose: bad argument");
     if (n == 0) return HS_OK;
     HS_REQUIRE(model && x && mask_out, "hs_mlp_propose: null argument");
@@ -411,7 +414,8 @@ extern "C" int hs_mlp_propose(hs_ctx *ctx, const float *model, const float *x, i
     cv.add(&logits, (size_t)n * MLP_C);
     HS_TRY(cv.commit(ctx));
     HS_TRY(mlp_forward_into(ctx, model, x, n, nullptr, a1, a2, a3, logits));
-    hipLaunchKernelGGL(mlp_select, dim3(blocks(n, 4)), dim3(256), 0, ctx->stream, logits, n, p_cum, mask_out);
+    hipLaunchKernelGGL(mlp_select, dim3(blocks(n, 4)), dim3(256), 0, ctx->stream, logits, x, n, p_cum, rho_split,
+                       p_cum_low, mask_out);
     HS_HIP(hipGetLastError());
     return HS_OK;
 }

@@ -76,7 +76,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_proposer_features": [P, P, I64, P, I64, P, P, P, I64, P, P, I32, I64, P, P, I32, I64, I64, I64, P],
         "hs_mlp_forward": [P, P, P, I64, P],
         "hs_mlp_train_step": [P, P, P, P, I64, F, P, P, I64, P, ctypes.POINTER(F)],
-        "hs_mlp_propose": [P, P, P, I64, F, P],
+        "hs_mlp_propose": [P, P, P, I64, F, F, F, P],
         "hs_followup_cells": [P, P, I64, F, P, I32, P, P, I32, D, P, P, I64, I32, P, P],
         "hs_far_fit": [P, P, I32, F, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32)],
         "hs_far": [P, P, I64, D, D, D, F, P],
@@ -396,13 +396,16 @@ def hs_mlp_train_step(ctx: Context, model, adam_m, adam_v, t: int, lr: float, x,
     return float(loss.value)
 
 
-def hs_mlp_propose(ctx: Context, model, x, p_cum: float, out=None):
-    """uint64 cell masks [n] (returned as an int64 device tensor with the same bits)."""
+def hs_mlp_propose(ctx: Context, model, x, p_cum: float, rho_split: float = float("-inf"), p_cum_low: float = None,
+                   out=None):
+    """uint64 cell masks [n] (returned as an int64 device tensor with the same bits); rows with
+    x[:, 2] < rho_split use p_cum_low."""
     _dev(model, torch.float32, "model")
     _dev(x, torch.float32, "x")
     out = torch.empty(x.shape[0], dtype=torch.int64, device=x.device) if out is None else out
-    _check(_lib.hs_mlp_propose(ctx.handle, _ptr(model), _ptr(x), x.shape[0], float(p_cum), _ptr(out)),
-           "hs_mlp_propose")
+    p_low = p_cum if p_cum_low is None else p_cum_low
+    _check(_lib.hs_mlp_propose(ctx.handle, _ptr(model), _ptr(x), x.shape[0], float(p_cum), float(rho_split),
+                               float(p_low), _ptr(out)), "hs_mlp_propose")
     return out
 
 

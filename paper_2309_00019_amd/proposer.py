@@ -24,23 +24,30 @@ LAYERS = [(16, 128), (128, 128), (128, 128), (128, 64)]
 
 @dataclass
 class Proposer:
+    """Model and operating point: coincidences with rho_c >= rho1 (the stage-1 threshold) keep
+    the cells of cumulative probability p_cum; weaker ones down to rho_low keep those of
+    p_cum_low (rho_low = rho1 gives a single tier)."""
     model: torch.Tensor                      # device float32 [hs.MLP_MODEL]
     p_cum: float = 0.99
     q_edges: tuple = Q_EDGES
     frac: float = 0.05
     meta: dict = field(default_factory=dict)
+    rho_low: float = 6.75
+    p_cum_low: float = 0.5
 
     @classmethod
     def load(cls, device, path: str = DEFAULT_PATH) -> "Proposer":
         z = np.load(path, allow_pickle=False)
         meta = {k[5:]: z[k].item() if z[k].ndim == 0 else z[k] for k in z.files if k.startswith("meta_")}
+        extra = {k: float(z[k]) for k in ("rho_low", "p_cum_low") if k in z.files}
         return cls(torch.as_tensor(z["model"].astype(np.float32), device=device), float(z["p_cum"]),
-                   tuple(float(v) for v in z["q_edges"]), float(z["frac"]), meta)
+                   tuple(float(v) for v in z["q_edges"]), float(z["frac"]), meta, **extra)
 
     def save(self, path: str = DEFAULT_PATH):
         extra = {"meta_" + k: np.asarray(v) for k, v in self.meta.items()}
         np.savez(path, model=self.model.detach().cpu().numpy(), p_cum=np.float64(self.p_cum),
-                 q_edges=np.asarray(self.q_edges, np.float64), frac=np.float64(self.frac), **extra)
+                 q_edges=np.asarray(self.q_edges, np.float64), frac=np.float64(self.frac),
+                 rho_low=np.float64(self.rho_low), p_cum_low=np.float64(self.p_cum_low), **extra)
 
 
 def cell_labels(coarse_mc, true_mc, true_q, frac: float, q_edges) -> np.ndarray:

@@ -42,8 +42,10 @@ class SearchConfig:
     step_sec: float = 0.1
     coinc_window_sec: float = 0.015
     cluster_sec: float = 1.0      # per-slide coincidence clustering window
-    edges: tuple = (6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0, 14.0, 16.0, 20.0)
+    edges: tuple = tuple(round(6.0 + 0.1 * i, 1) for i in range(81))   # background count grid, 6.0 .. 14.0
     chisq_rho_min: float = 5.5    # triggers at or above this SNR get the chi-square re-weighting (None: off)
+    far_x_min: float = 7.0        # Eq. (7) fit over the edges >= far_x_min with non-zero counts
+    far_x_fit: float = 8.0        # the fitted tail replaces the counted background at and above this
 
 
 @dataclass
@@ -61,6 +63,7 @@ class SearchResult:
     mf_ms: float = 0.0                   # device time inside matched-filter calls (events)
     mf_calls: int = 0
     mf_units: list = field(default_factory=list)   # (n, ids, bank) per matched-filter call
+    far: dict = None                                # background_far() output, when computed
 
 
 class _MFTimer:
@@ -125,6 +128,24 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
     if not with_chisq:
         return trig
     return trig, cat(chis, (0,)), cat(bins, (0, p))
+
+
+YEAR = 365.25 * 86400.0
+
+
+def background_far(ctx, res: "SearchResult", cfg: SearchConfig):
+    """Sec. IV: Eq. (7) fit of the background counts, hybrid FAR of every zero-lag coincidence
+    (device float64 per record, -1 for background records, per second) and the statistic
+    thresholds for inverse FARs of 1 and 10 years; None when the tail has fewer than two points."""
+    e = np.asarray(cfg.edges, np.float32)
+    try:
+        a, b, m = hs.hs_far_fit(e, res.bg_counts, cfg.far_x_min)
+    except hs.HsError:
+        return None
+    far = hs.hs_far(ctx, res.coincs, res.t_b, a, b, cfg.far_x_fit)
+    return dict(alpha=a, beta=b, n_fit=m, far=far, t_b=res.t_b,
+                ifar_1yr=hs.hs_far_threshold(a, b, res.t_b, YEAR),
+                ifar_10yr=hs.hs_far_threshold(a, b, res.t_b, 10 * YEAR))
 
 
 def _coinc(ctx, th, tl, n_tmpl, n_slides, step_sec, cfg, wrap, edges):
@@ -192,10 +213,12 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     use_p = proposer is not None
     t1h, t1l, c1 = stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg, timer, with_chisq=use_p)
     if use_p:
+        # two tiers: rho_c >= rho1 keeps the cells of probability p_cum, rho_low <= rho_c < rho1
+        # (marginal stage-1 coincidences, followed only through the proposer) those of p_cum_low
         feats = stage1_features(ctx, t1h, t1l, c1, coarse, n_seg, n, cfg)
-        masks = hs.hs_mlp_propose(ctx, proposer.model, feats, proposer.p_cum)
-        ids2, counts = hs.hs_followup_cells(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, fine.q, cfg.mc_frac,
-                                            proposer.q_edges, masks, seg_ticks, n_seg)
+        masks = hs.hs_mlp_propose(ctx, proposer.model, feats, proposer.p_cum, cfg.rho1, proposer.p_cum_low)
+        ids2, counts = hs.hs_followup_cells(ctx, c1, min(proposer.rho_low, cfg.rho1), coarse.mchirp, fine.mchirp,
+                                            fine.q, cfg.mc_frac, proposer.q_edges, masks, seg_ticks, n_seg)
     else:
         ids2, counts = hs.hs_followup(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, cfg.mc_frac, seg_ticks, n_seg)
     per_seg = [ids2[s, :counts[s]] for s in range(n_seg)]

@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-final", type=float, default=5e-5)
     ap.add_argument("--hit", type=float, default=0.99, help="held-out hit rate that sets P")
+    ap.add_argument("--rho-low", type=float, default=6.75,
+                    help="lower follow-up threshold of the second tier (set end to end on tuning injections)")
+    ap.add_argument("--p-low", type=float, default=0.5, help="P of the second tier")
     ap.add_argument("--out", default=None)
     ap.add_argument("--data", default=None, help="save the collected samples here (npz); with --reuse, load them")
     ap.add_argument("--reuse", action="store_true")
@@ -141,7 +144,7 @@ def main():
                 loss_first=hist[0], loss_last=hist[-1], train_seconds=t_train,
                 seeds="realisations: training 10000.., early stopping 40000.., held-out 20000.. (cfg 2)",
                 p_table=json.dumps([list(map(float, r)) for r in table]))
-    prop = proposer.Proposer(model, p_cum, proposer.Q_EDGES, cfg.mc_frac, meta)
+    prop = proposer.Proposer(model, p_cum, proposer.Q_EDGES, cfg.mc_frac, meta, args.rho_low, args.p_low)
     prop.save(args.out or proposer.DEFAULT_PATH)
     log(f"[done] P={p_cum} hit {hit:.4f} (plain rule {plain_hit:.4f}), {cells:.2f} cells, "
         f"{time.perf_counter() - t_start:.0f} s total")

@@ -51,7 +51,7 @@ def test_argument_errors_need_no_gpu():
     assert lib.hs_create(None, 0, None) == hs.HS_EINVAL
     assert b"null" in lib.hs_last_error().lower()
     assert lib.hs_mlp_forward(None, None, None, 4, None) == hs.HS_EINVAL
-    assert lib.hs_mlp_propose(None, None, None, 4, 0.9, None) == hs.HS_EINVAL
+    assert lib.hs_mlp_propose(None, None, None, 4, 0.9, 7.0, 0.5, None) == hs.HS_EINVAL
     assert lib.hs_mlp_train_step(None, None, None, None, 1, 0.01, None, None, 4, None, None) == hs.HS_EINVAL
     assert lib.hs_proposer_features(None, None, 1, None, 0, None, None, None, 0, None, None, 8, 1, None, None, 1,
                                     1, 1, 1, None) == hs.HS_EINVAL

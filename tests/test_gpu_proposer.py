@@ -148,26 +148,33 @@ def test_mlp_training_reduces_the_loss_and_is_deterministic(ctx):
     assert runs[0][0][-1] < 0.1 * runs[0][0][0]          # the FP64 oracle reaches 0.006 of the start
 
 
-@pytest.mark.parametrize("p_cum", [0.5, 0.9, 0.99])
-def test_mlp_propose_matches_oracle(ctx, p_cum):
+@pytest.mark.parametrize("p_cum,p_low", [(0.5, None), (0.9, None), (0.99, None), (0.99, 0.5)])
+def test_mlp_propose_matches_oracle(ctx, p_cum, p_low):
     import torch
     from paper_2309_00019_amd import hs
-    _say(f"mlp propose p={p_cum}")
+    _say(f"mlp propose p={p_cum} p_low={p_low}")
     n = 400
     m = _model(50)
     x = np.random.default_rng(51).normal(0.0, 1.0, (n, 16)).astype(np.float32)
+    x[:, 2] = np.random.default_rng(52).uniform(6.0, 8.0, n).astype(np.float32)
+    x[:4, 2] = 7.0
+    split = 7.0 if p_low is not None else float("-inf")
     got = hs.hs_mlp_propose(ctx, torch.as_tensor(m, device=ctx.device), torch.as_tensor(x, device=ctx.device),
-                            p_cum).cpu().numpy().view(np.uint64)
+                            p_cum, split, p_low).cpu().numpy().view(np.uint64)
     logits, _ = P.forward(m.astype(np.float64), x.astype(np.float64))
-    ref = P.select_cells(logits, p_cum)
+    if p_low is None:
+        ref = P.select_cells(logits, p_cum)
+    else:
+        ref = P.select_cells(logits, p_cum, x[:, 2], 7.0, p_low)
     prob = P.softmax(logits)
     fragile = 0
     for i in range(n):
+        pc = p_cum if (p_low is None or x[i, 2] >= np.float32(7.0)) else p_low
         ps = np.sort(prob[i])[::-1]
         cs = np.cumsum(ps)
-        k = int(np.searchsorted(cs, p_cum)) if cs[-1] >= p_cum else 63
+        k = int(np.searchsorted(cs, pc)) if cs[-1] >= pc else 63
         # the decision is fragile where float32 rounding can move the stopping point or the order
-        near_stop = abs(cs[min(k, 63)] - p_cum) < 1e-5 or (k > 0 and abs(cs[k - 1] - p_cum) < 1e-5)
+        near_stop = abs(cs[min(k, 63)] - pc) < 1e-5 or (k > 0 and abs(cs[k - 1] - pc) < 1e-5)
         # only the order across the boundary (last cell in vs first cell out) decides the mask
         near_tie = k < 63 and abs(ps[k] - ps[k + 1]) < 1e-6
         if near_stop or near_tie:

@@ -112,6 +112,17 @@ def test_select_cells_is_the_minimal_top_set():
     assert np.all(P.select_cells(logits, 2.0) == np.uint64(2 ** 64 - 1))
 
 
+def test_two_tier_selection_is_the_per_row_single_tier_selection():
+    g = np.random.default_rng(8)
+    logits = g.normal(0, 2.0, (60, 64))
+    rho = g.uniform(6.0, 8.0, 60).astype(np.float32)
+    rho[:3] = np.float32(7.0)                                  # the split itself belongs to the upper tier
+    got = P.select_cells(logits, 0.99, rho, 7.0, 0.5)
+    hi, lo = P.select_cells(logits, 0.99), P.select_cells(logits, 0.5)
+    assert np.array_equal(got, np.where(rho >= np.float32(7.0), hi, lo))
+    assert np.all(got[:3] == hi[:3])
+
+
 def test_select_cells_breaks_ties_by_lower_index():
     logits = np.zeros((1, 64))
     assert int(P.select_cells(logits, 3.0 / 64.0 - 1e-12)[0]) == 0b111
