@@ -227,14 +227,15 @@ def main():
         found_1yr = {"flat": 0, "hier": 0, "mlp": 0}
         followed = {"hier": [], "mlp": []}
 
-        def detected_1yr(res, t_inj):
-            """Injections with a zero-lag coincidence within 0.1 s whose hybrid FAR <= 1 / yr."""
-            f = search.background_far(ctx, res, cfg)
-            if f is None:
+        def detected_1yr(res, key, t_inj):
+            """Injections with a zero-lag coincidence within 0.1 s at or above the network SNR
+            whose fitted FAR is 1 / yr; the background model is the pipeline's own, from the
+            noise-only segment (slid injections would otherwise pollute their own background)."""
+            thr = ifar_thr.get(key)
+            if thr is None:
                 return 0
             rec = hs.as_records(res.coincs, hs.COINC)
-            far = f["far"].cpu().numpy()
-            ok = (rec["slide"] == 0) & (far >= 0) & (far <= 1.0 / search.YEAR)
+            ok = (rec["slide"] == 0) & (rec["snr_c"].astype(np.float64) >= thr)
             return int(sum(np.any(np.abs(rec["tick_h"][ok] - t) <= int(0.1 * tick)) for t in t_inj))
         for r in range(count):
             sh_, sl_, ip = workload.injection_realisation(100 + r, n, per_seg)
@@ -244,12 +245,12 @@ def main():
             for key, kw in (("hier", {}), ("mlp", {"proposer": prop})):
                 res = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l, cfg, **kw)
                 found[key] += found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick))
-                found_1yr[key] += detected_1yr(res, t_inj)
+                found_1yr[key] += detected_1yr(res, key, t_inj)
                 followed[key].append(int(sum(res.followed)))
             if not args.no_flat:
                 rf = search.flat_search(ctx, specs[0], specs[1], fine_h, fine_l, cfg)
                 found["flat"] += found_injections(hs.as_records(rf.coincs, hs.COINC), t_inj, int(0.1 * tick))
-                found_1yr["flat"] += detected_1yr(rf, t_inj)
+                found_1yr["flat"] += detected_1yr(rf, "flat", t_inj)
             if (r + 1) % 8 == 0:
                 log(f"[injections] {r + 1}/{count} realisations done")
         return found, followed, found_1yr
@@ -323,6 +324,9 @@ def main():
         out["speedup_vs_flat"] = round(flat["wall"] / wall_m, 3)
         if wall_h:
             out["speedup_plain_hier_vs_flat"] = round(flat["wall"] / wall_h, 3)
+    # IFAR >= 1 yr thresholds of each pipeline, from its noise-only background segment
+    ifar_thr = {k: (r.far["ifar_1yr"] if r is not None and r.far else None)
+                for k, r in (("mlp", res_m), ("hier", res_h), ("flat", flat["res"] if flat else None))}
     if args.injections > 0:
         n_inj = args.injections * args.per_seg
         log(f"[injections] {args.injections} realisations x {args.per_seg} (untimed)")

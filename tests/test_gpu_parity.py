@@ -96,6 +96,7 @@ CASES = [
     (2 ** 16, 2048.0, 20.0, "tau"),
     (2 ** 17, 512.0, 20.0, "tau"),
     (2 ** 18, 1024.0, 20.0, "tau"),
+    (2 ** 20, 2048.0, 20.0, "tau"),   # 512 s segments at 2048 Hz (the paper's segment length)
 ]
 
 
@@ -160,6 +161,40 @@ def test_matched_filter_candidates_follow_tolerance_rule(ctx, n, fs, f_low, kind
         dphi = np.angle(np.exp(1j * (ph - ref_ph)))
         assert np.all(np.abs(dphi) < 1e-3)
     assert worst < DELTA["f32"]
+
+
+@pytest.mark.parametrize("n,fs", [(2 ** 17, 512.0), (2 ** 20, 2048.0)])
+def test_snr_error_per_storage_precision(ctx, n, fs):
+    """SNR error of FP32 / BF16 / FP16 template storage (FP32 transform and accumulation) against
+    the FP64 oracle, over every sample with oracle rho >= 4; printed and held to the per-precision
+    tolerance."""
+    import torch
+    from paper_2309_00019_amd import hs
+    f_low = 20.0
+    bank = _bank_for("tau", n, fs, f_low, count=6, seed=19)
+    inj = dict(m1=bank.m1[3], m2=bank.m2[3], t_c=0.61 * n / fs, phi_c=0.5, snr=20.0)
+    s = _strain(19, 0, n, fs, f_low, glitch_rate=0.05, injections=[inj])
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
+    st = oracle.strain_fft(s, fs)
+    refs = []
+    for t in range(bank.n_tmpl):
+        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        refs.append(np.abs(oracle.snr_series(st, bank.spectrum(t), psd, n, fs, a, b)))
+    for dtype in ("f32", "bf16", "f16"):
+        pb = device_bank(ctx, bank, psd_d, f_low, dtype)
+        z = np.abs(hs.hs_snr_series(ctx, spec, n, fs, pb, ids).cpu().numpy())
+        worst, rms = 0.0, []
+        for t in range(bank.n_tmpl):
+            sel = refs[t] >= 4.0
+            rel = np.abs(z[t][sel] / refs[t][sel] - 1.0)
+            worst = max(worst, float(rel.max()) if sel.any() else 0.0)
+            rms.append(rel)
+        rms = float(np.sqrt(np.mean(np.concatenate(rms) ** 2)))
+        _say(f"snr error n={n} {dtype}: max {worst:.2e} rms {rms:.2e} (samples with rho >= 4)")
+        assert worst <= DELTA[dtype], (dtype, worst)
 
 
 # ------------------------------------------------------------------------------------------
