@@ -2,10 +2,11 @@
 //
 // Sec. II down-weights triggers with the chi-square test it cites; the test splits the template
 // band into p bins of equal template power and compares each bin's share of the complex SNR with
-// 1/p of the total.  Only triggers (a few per template) are tested, so each trigger gets one
-// workgroup that evaluates the p band-limited SNRs z_l at its sample by direct sums over the band:
-// q_k = d~_k conj(w~_k) times the phasor W_N^{(k m) mod N} from the two-level twiddle table,
-// accumulated in float64 per bin, reduced across the workgroup with wavefront shuffles.
+// 1/p of the total.  Only triggers at or above rho_min are tested: they are compacted first, then
+// one workgroup per (trigger, bin) evaluates the band-limited SNR z_l at the trigger's sample by
+// a direct sum over the bin (float64 phasor recurrence and accumulation), and a last kernel forms
+// chi2, the per-bin terms and the re-weighted SNR.  Splitting by bin gives p workgroups per
+// trigger, enough to fill the GPU when only a few hundred triggers need the test.
 #include <cmath>
 
 #include "dft.h"
@@ -14,120 +15,173 @@
 
 namespace hs {
 
-template <typename ST, int P>
-__global__ __launch_bounds__(256) void chisq_kernel(const float2 *__restrict__ dspec, int64_t n,
-                                                    const typename ST::elem *__restrict__ spectra,
-                                                    const int64_t *__restrict__ offset, const int32_t *__restrict__ k0,
-                                                    const int32_t *__restrict__ klo, const int32_t *__restrict__ khi,
-                                                    const float *__restrict__ r2s, const int32_t *__restrict__ edges,
-                                                    const hs_trigger *trig, int32_t n_tmpl, int64_t seg_t0,
-                                                    int64_t tps, float rho_min, const float2 *__restrict__ twlo,
-                                                    const float2 *__restrict__ twhi, float *__restrict__ chisq_out,
-                                                    hs_trigger *trig_out, float *__restrict__ bins_out,
-                                                    int32_t *__restrict__ bad) {
-    __shared__ double red[4][2 * P];
-    const int64_t i = blockIdx.x;
+static constexpr int CQ_THREADS = 256;
+
+// Triggers below rho_min (and invalid ones) are copied through here; the others are flagged
+// for the band-limited sums.
+__global__ void chisq_select(const hs_trigger *trig, int64_t n_trig, int32_t n_tmpl, int64_t seg_t0, int64_t tps,
+                             int64_t n, float rho_min, int p, uint32_t *__restrict__ flag,
+                             float *__restrict__ chisq_out, hs_trigger *trig_out, float *__restrict__ bins_out,
+                             int32_t *__restrict__ bad) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_trig) return;
     const hs_trigger tr = trig[i];
-    const int tid = threadIdx.x;
-    bool skip = !(tr.snr >= rho_min);
-    int64_t m = 0;
-    if (!skip) {
+    bool active = tr.snr >= rho_min;
+    if (active) {
         const int64_t dt = tr.tick - seg_t0;
         if (tr.tmpl < 0 || tr.tmpl >= n_tmpl) {
-            if (tid == 0) atomicOr(bad, 1);
-            skip = true;
+            atomicOr(bad, 1);
+            active = false;
         } else if (dt < 0 || dt % tps != 0 || dt / tps >= n) {
-            if (tid == 0) atomicOr(bad, 2);
-            skip = true;
-        } else {
-            m = dt / tps;
+            atomicOr(bad, 2);
+            active = false;
         }
     }
-    if (skip) {
-        if (tid == 0) {
-            chisq_out[i] = 0.0f;
-            trig_out[i] = tr;
-        }
-        if (bins_out && tid < P) bins_out[i * P + tid] = 0.0f;
-        return;
-    }
-    const int t = tr.tmpl;
-    const int32_t *e = edges + (int64_t)t * (P + 1);
-    const int64_t base = offset[t] - k0[t];
-    const uint64_t mask = (uint64_t)n - 1;
-    // every bin is clamped to the template's band, which lies inside [1, n/2 - 1]
-    const int64_t band_lo = klo[t] > 1 ? klo[t] : 1;
-    const int64_t band_hi = khi[t] < n / 2 - 1 ? khi[t] : n / 2 - 1;
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        double ar = 0.0, ai = 0.0;
-        const int64_t b0 = e[l] > band_lo ? e[l] : band_lo;
-        const int64_t b1 = e[l + 1] < band_hi + 1 ? e[l + 1] : band_hi + 1;
-        for (int64_t k = b0 + tid; k < b1; k += 256) {
-            const float2 q = cmulc(dspec[k], ST::load(spectra, base + k));
-            const uint64_t idx = ((uint64_t)k * (uint64_t)m) & mask;
-            const float2 w = cmul(twhi[idx >> 10], twlo[idx & 1023]);
-            const float2 v = cmul(q, w);
-            ar += (double)v.x;
-            ai += (double)v.y;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            ar += __shfl_down(ar, o);
-            ai += __shfl_down(ai, o);
-        }
-        if ((tid & 63) == 0) {
-            red[tid >> 6][2 * l] = ar;
-            red[tid >> 6][2 * l + 1] = ai;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        const double s = sqrt((double)r2s[t]);  // undoes the storage scale of the template
-        double zr[P], zi[P], Zr = 0.0, Zi = 0.0;
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-            zr[l] = (red[0][2 * l] + red[1][2 * l] + red[2][2 * l] + red[3][2 * l]) * s;
-            zi[l] = (red[0][2 * l + 1] + red[1][2 * l + 1] + red[2][2 * l + 1] + red[3][2 * l + 1]) * s;
-            Zr += zr[l];
-            Zi += zi[l];
-        }
-        double chi2 = 0.0;
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-            const double dr = zr[l] - Zr / P, di = zi[l] - Zi / P;
-            chi2 += dr * dr + di * di;
-            if (bins_out) bins_out[i * P + l] = (float)(P * (dr * dr + di * di));
-        }
-        const double c = chi2 * P / (2.0 * P - 2.0);
-        double rw = (double)tr.snr;
-        if (c >= 1.0) rw = rw / pow((1.0 + c * c * c) / 2.0, 1.0 / 6.0);
-        chisq_out[i] = (float)c;
-        hs_trigger o = tr;
-        o.snr = (float)rw;
-        trig_out[i] = o;
+    flag[i] = active ? 1u : 0u;
+    if (!active) {
+        chisq_out[i] = 0.0f;
+        trig_out[i] = tr;
+        if (bins_out)
+            for (int l = 0; l < p; ++l) bins_out[i * p + l] = 0.0f;
     }
 }
 
+__global__ void chisq_compact(const uint32_t *__restrict__ flag, const uint64_t *__restrict__ off, int64_t n,
+                              uint32_t *__restrict__ act) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) act[off[i]] = (uint32_t)i;
+}
+
+// Groups of at most CQ_GROUP consecutive active triggers of one template share each pass over
+// the template's band (active triggers are in trigger order, so a template's are contiguous).
+static constexpr int CQ_GROUP = 8;
+
+__global__ void chisq_group_starts(const hs_trigger *trig, const uint32_t *__restrict__ act, int64_t n_act,
+                                   uint32_t *__restrict__ start) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n_act) return;
+    // a new group at the start of each run of one template and every CQ_GROUP triggers within it
+    // (a run is at most one segment's triggers of a template: the backward walk is short)
+    const int32_t t = trig[act[a]].tmpl;
+    int64_t r = a;
+    while (r > 0 && trig[act[r - 1]].tmpl == t) --r;
+    start[a] = ((a - r) % CQ_GROUP == 0) ? 1u : 0u;
+}
+
+__global__ void chisq_group_list(const uint32_t *__restrict__ start, const uint64_t *__restrict__ off, int64_t n_act,
+                                 uint32_t *__restrict__ gfirst) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a < n_act && start[a]) gfirst[off[a]] = (uint32_t)a;
+}
+
+// z_l for one (bin l, group of active triggers of one template): sum over the bins of l of
+// q_k exp(+2 pi i k m / N), q_k = d~_k conj(w~_k) formed once per bin in float32 and shared by the
+// group's triggers; everything after it in float64.  Each thread owns the bins k0 + tid + 256 j;
+// per trigger its phasor starts from an exact float64 sincospi of (k m mod N) / N and advances by
+// the fixed step exp(2 pi i (256 m mod N) / N), so no twiddle table is read.
 template <typename ST>
-static int launch_chisq(hs_ctx *ctx, int p, int64_t n_trig, const float2 *d, int64_t n, const hs_bank *bank,
-                        const hs_trigger *trig, int64_t seg_t0, int64_t tps, float rho_min, const float2 *twlo,
-                        const float2 *twhi, float *chisq_out, hs_trigger *trig_out, float *bins_out,
-                        int32_t *bad) {
-    const auto *sp = static_cast<const typename ST::elem *>(bank->spectra);
-#define HS_CQ(PP)                                                                                                  \
-    case PP:                                                                                                       \
-        hipLaunchKernelGGL((chisq_kernel<ST, PP>), dim3((unsigned)n_trig), dim3(256), 0, ctx->stream, d, n, sp,     \
-                           bank->offset, bank->k0, bank->k_lo, bank->k_hi, bank->rho2_scale, bank->chisq_edges,    \
-                           trig, bank->n_tmpl, seg_t0,                                                           \
-                           tps, rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad);                         \
-        break;
-    switch (p) {
-        HS_CQ(2) HS_CQ(4) HS_CQ(8) HS_CQ(16)
-    default: return set_error(HS_EINVAL, "hs_chisq: chisq_bins must be 2, 4, 8 or 16 (got %d)", p);
+__global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
+    const float2 *__restrict__ dspec, int64_t n, const typename ST::elem *__restrict__ spectra,
+    const int64_t *__restrict__ offset, const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
+    const int32_t *__restrict__ khi, const int32_t *__restrict__ edges, int p, const hs_trigger *trig,
+    const uint32_t *__restrict__ act, int64_t n_act, const uint32_t *__restrict__ gfirst, int64_t seg_t0,
+    int64_t tps, double2 *__restrict__ zl) {
+    __shared__ double red[CQ_THREADS / 64][CQ_GROUP][2];
+    const int64_t a0 = gfirst[blockIdx.x];
+    const int l = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int t = trig[act[a0]].tmpl;
+    int g = 1;
+    while (g < CQ_GROUP && a0 + g < n_act && trig[act[a0 + g]].tmpl == t) ++g;
+    const int32_t *e = edges + (int64_t)t * (p + 1);
+    const int64_t base = offset[t] - k0[t];
+    // every bin is clamped to the template's band, which lies inside [1, n/2 - 1]
+    const int64_t band_lo = klo[t] > 1 ? klo[t] : 1;
+    const int64_t band_hi = khi[t] < n / 2 - 1 ? khi[t] : n / 2 - 1;
+    const int64_t b0 = e[l] > band_lo ? e[l] : band_lo;
+    const int64_t b1 = e[l + 1] < band_hi + 1 ? e[l + 1] : band_hi + 1;
+    const uint64_t mask = (uint64_t)n - 1;
+    const double inv_half_n = 2.0 / (double)n;
+    const int64_t k_first = b0 + tid;
+    double ar[CQ_GROUP], ai[CQ_GROUP], wr[CQ_GROUP], wi[CQ_GROUP], sr[CQ_GROUP], si[CQ_GROUP];
+#pragma unroll
+    for (int j = 0; j < CQ_GROUP; ++j) {
+        ar[j] = ai[j] = 0.0;
+        wr[j] = 1.0;
+        wi[j] = sr[j] = si[j] = 0.0;
+        if (j < g && k_first < b1) {
+            const uint64_t m = (uint64_t)((trig[act[a0 + j]].tick - seg_t0) / tps);
+            sincospi((double)(((uint64_t)k_first * m) & mask) * inv_half_n, &wi[j], &wr[j]);
+            sincospi((double)(((uint64_t)CQ_THREADS * m) & mask) * inv_half_n, &si[j], &sr[j]);
+        }
     }
-#undef HS_CQ
-    HS_HIP(hipGetLastError());
-    return HS_OK;
+    for (int64_t k = k_first; k < b1; k += CQ_THREADS) {
+        const float2 q = cmulc(dspec[k], ST::load(spectra, base + k));
+        const double qr = (double)q.x, qi = (double)q.y;
+#pragma unroll
+        for (int j = 0; j < CQ_GROUP; ++j) {
+            if (j < g) {
+                ar[j] += qr * wr[j] - qi * wi[j];
+                ai[j] += qr * wi[j] + qi * wr[j];
+                const double nr = wr[j] * sr[j] - wi[j] * si[j];
+                wi[j] = wr[j] * si[j] + wi[j] * sr[j];
+                wr[j] = nr;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CQ_GROUP; ++j) {
+        if (j < g) {
+            double x = ar[j], y = ai[j];
+            for (int o = 32; o > 0; o >>= 1) {
+                x += __shfl_down(x, o);
+                y += __shfl_down(y, o);
+            }
+            if ((tid & 63) == 0) {
+                red[tid >> 6][j][0] = x;
+                red[tid >> 6][j][1] = y;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < g) {
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < CQ_THREADS / 64; ++w) {
+            x += red[w][tid][0];
+            y += red[w][tid][1];
+        }
+        zl[(a0 + tid) * p + l] = double2{x, y};
+    }
+}
+
+// chi2 = p sum_l |z_l - z/p|^2, chi2_r = chi2 / (2p - 2), Eq. (4) re-weighting; one thread per
+// active trigger.
+__global__ void chisq_finish(const double2 *__restrict__ zl, const uint32_t *__restrict__ act, int64_t n_act, int p,
+                             const hs_trigger *trig, const float *__restrict__ r2s, float *__restrict__ chisq_out,
+                             hs_trigger *trig_out, float *__restrict__ bins_out) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n_act) return;
+    const uint32_t i = act[a];
+    const hs_trigger tr = trig[i];
+    const double s = sqrt((double)r2s[tr.tmpl]);  // undoes the storage scale of the template
+    double Zr = 0.0, Zi = 0.0;
+    for (int l = 0; l < p; ++l) {
+        Zr += zl[a * p + l].x * s;
+        Zi += zl[a * p + l].y * s;
+    }
+    double chi2 = 0.0;
+    for (int l = 0; l < p; ++l) {
+        const double dr = zl[a * p + l].x * s - Zr / p, di = zl[a * p + l].y * s - Zi / p;
+        chi2 += dr * dr + di * di;
+        if (bins_out) bins_out[(int64_t)i * p + l] = (float)(p * (dr * dr + di * di));
+    }
+    const double c = chi2 * p / (2.0 * p - 2.0);
+    double rw = (double)tr.snr;
+    if (c >= 1.0) rw = rw / pow((1.0 + c * c * c) / 2.0, 1.0 / 6.0);
+    chisq_out[i] = (float)c;
+    hs_trigger o = tr;
+    o.snr = (float)rw;
+    trig_out[i] = o;
 }
 
 }  // namespace hs
@@ -143,36 +197,80 @@ extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, con
     HS_REQUIRE(spec && trig && chisq_out && trig_out, "hs_chisq: null argument");
     HS_REQUIRE(is_pow2(n) && n >= 8192 && n <= (int64_t(1) << 22), "hs_chisq: n must be a power of two in [2^13, 2^22]");
     HS_REQUIRE(bank->n == n && bank->fs == fs, "hs_chisq: bank prepared for another n or fs");
-    HS_REQUIRE(bank->chisq_bins >= 2 && bank->chisq_edges, "hs_chisq: bank has no chi-square bins");
+    HS_REQUIRE(bank->chisq_bins >= 2 && bank->chisq_bins <= 16 && bank->chisq_edges,
+               "hs_chisq: bank has no chi-square bins (2..16)");
     HS_REQUIRE(ticks_per_sample > 0, "hs_chisq: ticks_per_sample must be positive");
+    HS_REQUIRE(bank->dtype == HS_F32 || bank->dtype == HS_BF16 || bank->dtype == HS_F16, "hs_chisq: bad bank dtype");
     HS_HIP(hipSetDevice(ctx->device));
-    const int log2N = ilog2(n);
-    const float2 *twlo, *twhi;
-    HS_TRY(twiddles_f32(ctx, log2N, &twlo));
-    HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
+    const int p = bank->chisq_bins;
+    uint32_t *flag, *act;
+    uint64_t *off, *tmp;
     int32_t *bad;
     Carver cv;
+    cv.add(&flag, n_trig);
+    cv.add(&off, n_trig + 1);
+    cv.add(&act, n_trig);
+    cv.add(&tmp, scan_tmp_elems(n_trig));
     cv.add(&bad, 1);
     HS_TRY(cv.commit(ctx));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
+    const unsigned g = (unsigned)cdiv(n_trig, 256);
+    hipLaunchKernelGGL(chisq_select, dim3(g), dim3(256), 0, ctx->stream, trig, n_trig, bank->n_tmpl, seg_t0,
+                       ticks_per_sample, n, rho_min, p, flag, chisq_out, trig_out, bins_out, bad);
+    HS_HIP(hipGetLastError());
+    HS_TRY(exclusive_scan_u32(ctx, flag, n_trig, off, tmp));
+    hipLaunchKernelGGL(chisq_compact, dim3(g), dim3(256), 0, ctx->stream, flag, off, n_trig, act);
+    HS_HIP(hipGetLastError());
+    uint64_t n_act = 0;
+    int32_t hbad = 0;
+    HS_TRY(read_back(ctx, off + n_trig, &n_act, sizeof(n_act)));
+    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_REQUIRE(hbad == 0, "hs_chisq: trigger template outside the bank or tick outside this segment (code %d)", hbad);
+    if (n_act == 0) return HS_OK;
+    double2 *zl;
+    uint32_t *gstart, *gfirst;
+    uint64_t *goff;
+    Carver cv2;  // re-carves the same buffers first, then the groups and the bin sums
+    cv2.add(&flag, n_trig);
+    cv2.add(&off, n_trig + 1);
+    cv2.add(&act, n_trig);
+    cv2.add(&tmp, scan_tmp_elems(n_trig));
+    cv2.add(&bad, 1);
+    cv2.add(&zl, (size_t)n_act * p);
+    cv2.add(&gstart, (size_t)n_act);
+    cv2.add(&goff, (size_t)n_act + 1);
+    cv2.add(&gfirst, (size_t)n_act);
+    HS_TRY(cv2.commit(ctx));
+    const unsigned ga = (unsigned)cdiv((int64_t)n_act, 256);
+    hipLaunchKernelGGL(chisq_group_starts, dim3(ga), dim3(256), 0, ctx->stream, trig, act, (int64_t)n_act, gstart);
+    HS_HIP(hipGetLastError());
+    HS_TRY(exclusive_scan_u32(ctx, gstart, (int64_t)n_act, goff, tmp));
+    hipLaunchKernelGGL(chisq_group_list, dim3(ga), dim3(256), 0, ctx->stream, gstart, goff, (int64_t)n_act, gfirst);
+    HS_HIP(hipGetLastError());
+    uint64_t n_groups = 0;
+    HS_TRY(read_back(ctx, goff + n_act, &n_groups, sizeof(n_groups)));
+    const dim3 gs((unsigned)n_groups, (unsigned)p);  // (group of triggers, bin): x holds the large count
     const float2 *d = static_cast<const float2 *>(spec);
     switch (bank->dtype) {
     case HS_F32:
-        HS_TRY(launch_chisq<StoreF32>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                      rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
+        hipLaunchKernelGGL(chisq_bin_sums<StoreF32>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
+                           static_cast<const float2 *>(bank->spectra), bank->offset, bank->k0, bank->k_lo, bank->k_hi,
+                           bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
         break;
     case HS_BF16:
-        HS_TRY(launch_chisq<StoreBF16>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                       rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
+        hipLaunchKernelGGL(chisq_bin_sums<StoreBF16>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
+                           static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                           bank->k_hi, bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
         break;
-    case HS_F16:
-        HS_TRY(launch_chisq<StoreF16>(ctx, bank->chisq_bins, n_trig, d, n, bank, trig, seg_t0, ticks_per_sample,
-                                      rho_min, twlo, twhi, chisq_out, trig_out, bins_out, bad));
+    default:
+        hipLaunchKernelGGL(chisq_bin_sums<StoreF16>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
+                           static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                           bank->k_hi, bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
         break;
-    default: return set_error(HS_EINVAL, "hs_chisq: bad bank dtype");
     }
-    int32_t hbad = 0;
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
-    HS_REQUIRE(hbad == 0, "hs_chisq: trigger template outside the bank or tick outside this segment (code %d)", hbad);
+    HS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(chisq_finish, dim3((unsigned)cdiv((int64_t)n_act, 256)), dim3(256), 0, ctx->stream, zl, act,
+                       (int64_t)n_act, p, trig, bank->rho2_scale, chisq_out, trig_out, bins_out);
+    HS_HIP(hipGetLastError());
     return HS_OK;
 }
