@@ -72,6 +72,28 @@ def mf_bytes(units, hs):
     return total
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "mf_pass_a_b_flat_30000x2x256s_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per matched-filter launch pair recorded in the committed rocprofv3 counter summary,
+    or None when mf.hip has changed since the counters were taken (source hash recorded there)."""
+    import hashlib
+    import re
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2309_00019_amd", "csrc", "mf.hip")
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    h = re.search(r"mf\.hip sha256: ([0-9a-f]{64})", text)
+    b = re.search(r"HBM bytes per launch pair: ([0-9]+)", text)
+    if not h or not b or h.group(1) != digest:
+        return None
+    return int(b.group(1))
+
+
 def found_injections(coincs_rec, inj_ticks, tol_ticks, snr_c_min=8.0):
     zl = coincs_rec[(coincs_rec["slide"] == 0) & (coincs_rec["snr_c"] >= snr_c_min)]
     found = 0
@@ -285,7 +307,7 @@ def main():
     launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel())) for n_, ids, _ in src.mf_units)
     achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "kernel": "matched filter: mf_pass_a + mf_pass_b over one template batch",
             "per_launch_ms": round(src.mf_ms / max(1, launches), 4), "launches": launches,
             "bytes_per_launch": int(mf_b / max(1, launches))}
