@@ -76,9 +76,10 @@ TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
                                "mf_pass_a_b_flat_30000x2x256s_hbm_traffic.md")
 
 
-def measured_traffic():
-    """HBM bytes per matched-filter launch pair recorded in the committed rocprofv3 counter summary,
-    or None when mf.hip has changed since the counters were taken (source hash recorded there)."""
+def measured_traffic_per_template():
+    """HBM bytes per template of the matched filter recorded in the committed rocprofv3 counter
+    summary, or None when mf.hip has changed since the counters were taken (source hash recorded
+    there)."""
     import hashlib
     import re
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2309_00019_amd", "csrc", "mf.hip")
@@ -88,7 +89,7 @@ def measured_traffic():
     except OSError:
         return None
     h = re.search(r"mf\.hip sha256: ([0-9a-f]{64})", text)
-    b = re.search(r"HBM bytes per launch pair: ([0-9]+)", text)
+    b = re.search(r"HBM bytes per template[^:]*: ([0-9]+)", text)
     if not h or not b or h.group(1) != digest:
         return None
     return int(b.group(1))
@@ -134,7 +135,7 @@ def main():
         sys.exit(2)
     import torch
     import synth
-    from paper_2309_00019_amd import hs, search, workload
+    from paper_2309_00019_amd import autotune, hs, search, workload
     from paper_2309_00019_amd.proposer import Proposer
 
     if args.calib_copy:
@@ -185,8 +186,14 @@ def main():
                                              [psd_h[: n1 // 2 + 1].contiguous(), psd_l[: n1 // 2 + 1].contiguous()],
                                              args.dtype, args.chunk)
     prop = Proposer.load(dev)
+    # schedule of the matched filter, measured on every 10th fine template and the background data
+    spec_tune = hs.hs_whiten(ctx, strain_h, fs, f_low, psd_h)
+    tune_ids = torch.arange(0, args.fine, 10, dtype=torch.int32, device=dev)
+    best_mb, tune_table = autotune.tune_mf_batch(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
+    del spec_tune
     torch.cuda.synchronize()
-    log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s; proposer P = {prop.p_cum}")
+    log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s; proposer P = {prop.p_cum}; "
+        f"matched-filter batch {best_mb} MB ({tune_table} us/template)")
 
     def whiten_both():
         ph = hs.hs_welch_psd(ctx, strain_h, fs, L)
@@ -304,10 +311,13 @@ def main():
     # flat pass (the calls of the hierarchical pass when the flat search is skipped)
     src = flat["res_t"] if flat else res_mt
     mf_b = mf_bytes(src.mf_units, hs)
-    launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel())) for n_, ids, _ in src.mf_units)
+    launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel(), ctx)) for n_, ids, _ in src.mf_units)
     achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
+    per_tmpl = measured_traffic_per_template()
+    n_tmpl_mf = sum(ids.numel() for _, ids, _ in src.mf_units)
+    traffic = None if per_tmpl is None else int(per_tmpl * n_tmpl_mf / max(1, launches))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "matched filter: mf_pass_a + mf_pass_b over one template batch",
             "per_launch_ms": round(src.mf_ms / max(1, launches), 4), "launches": launches,
             "bytes_per_launch": int(mf_b / max(1, launches))}
@@ -332,6 +342,7 @@ def main():
                    "value_definition": "flat-equivalent: fine templates x detectors x seconds / wall per step",
                    "followed_templates": [int(c) for c in res_m.followed],
                    "proposer_p_cum": prop.p_cum,
+                   "mf_batch_mb": best_mb, "mf_autotune_us_per_template": tune_table,
                    "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }

@@ -103,6 +103,14 @@ const char *hs_last_error(void);
 /* ABI version; changes whenever a struct or signature changes. */
 int hs_abi_version(void);
 
+/* Matched-filter schedule: bytes of the pass-A -> pass-B intermediate per batch
+ * (batch = bytes / (8 n) templates, at least 1).  Default 128 MiB, or the
+ * HS_MF_BATCH_MB environment variable at hs_create; set by the autotuner.
+ * HS_EINVAL if bytes < 1 MiB or > 64 GiB.  hs_get_mf_batch_bytes returns the
+ * current value (0 for a NULL context). */
+int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes);
+int64_t hs_get_mf_batch_bytes(const hs_ctx *ctx);
+
 /*
  * One-sided Welch PSD (the weight S_n of Eq. (2); the paper does not say how
  * it is estimated).  Segments of seg_len samples every seg_len/2 samples,

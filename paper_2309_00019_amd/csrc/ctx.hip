@@ -326,7 +326,17 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 3; }
+int hs_abi_version(void) { return 4; }
+
+int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
+    HS_REQUIRE(ctx, "hs_set_mf_batch_bytes: null context");
+    HS_REQUIRE(bytes >= (int64_t(1) << 20) && bytes <= (int64_t(1) << 36),
+               "hs_set_mf_batch_bytes: %lld bytes outside [1 MiB, 64 GiB]", (long long)bytes);
+    ctx->mf_batch_bytes = (size_t)bytes;
+    return HS_OK;
+}
+
+int64_t hs_get_mf_batch_bytes(const hs_ctx *ctx) { return ctx ? (int64_t)ctx->mf_batch_bytes : 0; }
 
 int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     if (!ctx) return hs::set_error(HS_EINVAL, "hs_create: ctx is NULL");

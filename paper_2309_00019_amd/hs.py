@@ -27,7 +27,7 @@ EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_wel
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
            "hs_chisq", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
            "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells", "hs_far_fit", "hs_far",
-           "hs_far_threshold"]
+           "hs_far_threshold", "hs_set_mf_batch_bytes", "hs_get_mf_batch_bytes"]
 MLP_FEATURES, MLP_CELLS, MLP_PARAMS = 16, 64, 43456
 MLP_MODEL = 32 + MLP_PARAMS
 
@@ -81,11 +81,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_far_fit": [P, P, I32, F, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32)],
         "hs_far": [P, P, I64, D, D, D, F, P],
         "hs_far_threshold": [D, D, D, D],
+        "hs_set_mf_batch_bytes": [P, I64],
+        "hs_get_mf_batch_bytes": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = {"hs_last_error": ctypes.c_char_p, "hs_far_threshold": ctypes.c_double}.get(name, ctypes.c_int)
+        fn.restype = {"hs_last_error": ctypes.c_char_p, "hs_far_threshold": ctypes.c_double,
+                      "hs_get_mf_batch_bytes": ctypes.c_int64}.get(name, ctypes.c_int)
     _lib = lib
     return lib
 
@@ -176,11 +179,22 @@ class PreparedBank:
                             chisq_bins=chisq_bins, chisq_edges=edges)
 
 
-def mf_batch_templates(n: int, n_ids: int) -> int:
+def mf_batch_templates(n: int, n_ids: int, ctx: "Context" = None) -> int:
     """Templates per pass-A/pass-B launch in hs_matched_filter (same rule as the library)."""
-    mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
-    budget = (mb << 20) if mb > 0 else (128 << 20)
+    if ctx is not None:
+        budget = hs_get_mf_batch_bytes(ctx)
+    else:
+        mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
+        budget = (mb << 20) if mb > 0 else (128 << 20)
     return max(1, min(65535, n_ids, budget // (n * 8)))
+
+
+def hs_set_mf_batch_bytes(ctx: "Context", nbytes: int):
+    _check(_lib.hs_set_mf_batch_bytes(ctx.handle, int(nbytes)), "hs_set_mf_batch_bytes")
+
+
+def hs_get_mf_batch_bytes(ctx: "Context") -> int:
+    return int(_lib.hs_get_mf_batch_bytes(ctx.handle))
 
 
 def hs_abi_version() -> int:
