@@ -64,6 +64,7 @@ class SearchResult:
     mf_calls: int = 0
     mf_units: list = field(default_factory=list)   # (n, ids, bank) per matched-filter call
     far: dict = None                                # background_far() output, when computed
+    fine_ids: list = None                           # per segment: followed fine template ids (device)
 
 
 class _MFTimer:
@@ -229,4 +230,4 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     apps = 2 * int(sum(counts))
     return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
                         stage1_template_seconds=2 * n_seg * coarse.n_tmpl * T, stage1_coincs=c1, followed=counts,
-                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units)
+                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units, fine_ids=per_seg)
