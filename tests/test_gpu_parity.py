@@ -231,13 +231,14 @@ def test_cluster_exact_on_identical_inputs(ctx, seed, n, W):
     (1, 13107200, 2000, 5120, 768, 51200),      # 256 s, 2000 slides of 0.1 s, 15 ms window
     (2, 30001, 40, 700, 200, 2500),             # wrap not a multiple of the clustering window
     (3, 9000, 30, 1000, 100, 4000),             # 2 cw + 1 > wrap/2: few tiles
+    (4, 13107200, 100000, 131, 768, 51200),     # 100,000 slides: the shifts wrap the data 51 times
 ])
 def test_timeslide_coinc_exact_on_identical_inputs(ctx, seed, wrap, K, step, window, cw):
     from paper_2309_00019_amd import hs
     _say(f"coinc seed={seed}")
     g = np.random.default_rng(200 + seed)
     n_tmpl = 30
-    per = 40 if wrap > 10 ** 6 else 8
+    per = 6 if K > 10 ** 4 else (40 if wrap > 10 ** 6 else 8)   # the oracle's per-slide loop bounds the 100k case
     th = synth.synthetic_triggers(g, n_tmpl, wrap, per, 25, wrap)
     tl = synth.synthetic_triggers(g, n_tmpl, wrap, per, 25, wrap)
     tl["snr"][::5] = th["snr"][0]  # exact stat ties
@@ -475,3 +476,31 @@ def test_background_fit_and_far_end_to_end_on_identical_triggers(ctx):
     want = F.far(rc["stat"][rc["slide"] == 0], rc["stat"][rc["slide"] >= 1], t_b, ra, rb, 8.0)
     assert fg.sum() == len(want) and fg.sum() > 0
     assert np.allclose(far[fg], want, rtol=1e-12, atol=0)
+
+
+def test_matched_filter_does_not_depend_on_the_batch_budget(ctx):
+    """The autotuner's knob changes only the schedule: candidates are identical for any budget."""
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("batch budget invariance")
+    n, fs, f_low = 2 ** 16, 2048.0, 20.0
+    bank = _bank_for("tau", n, fs, f_low, count=37, seed=21)
+    s = _strain(21, 0, n, fs, f_low, glitch_rate=0.1)
+    psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
+    old = hs.hs_get_mf_batch_bytes(ctx)
+    out = []
+    try:
+        for mb in (1, 3, 64):      # 2, 6 and all 37 templates per launch at n = 2^16
+            hs.hs_set_mf_batch_bytes(ctx, mb << 20)
+            assert hs.hs_get_mf_batch_bytes(ctx) == mb << 20
+            c = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 4.0), hs.CANDIDATE)
+            out.append(np.sort(c, order=["tpos", "m"]))
+    finally:
+        hs.hs_set_mf_batch_bytes(ctx, old)
+    assert len(out[0]) > 100
+    assert all(np.array_equal(out[0], o) for o in out[1:])
+    with pytest.raises(hs.HsError):
+        hs.hs_set_mf_batch_bytes(ctx, 1000)
