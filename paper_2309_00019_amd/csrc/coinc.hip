@@ -12,7 +12,9 @@
 // (tmpl, tick_h, tick_l)) reuses the tile idea of trigger clustering: bins are (slide, tile of
 // W_c ticks of tick_h); a bin's best member is found with a 64-bit atomicMax on
 // (stat bits, 0xFFFF - tmpl, 0xFFFF - tick_h offset in the tile) plus an atomicMin on tick_l for
-// exact ties; only that champion can survive, and it scans the neighbouring tiles of its slide.
+// exact ties; only that champion can survive, and it checks the neighbouring tiles of its slide
+// (against their champions first, scanning a tile's members only when its better champion lies
+// out of reach).
 // Survivors are compacted in bin order, i.e. sorted by (slide, tick_h).
 #include "hs_internal.h"
 
@@ -203,6 +205,19 @@ __global__ void co_champion(const RawCoinc *__restrict__ raw, int64_t P, const h
         if (dup) continue;
         seen[ns++] = t2;
         const int64_t nb = slide0 + t2;
+        if (start[nb] == start[nb + 1]) continue;
+        // the neighbour bin's champion is its best member in the same order: if it is not
+        // better, no member is; if it is better and within reach, this one loses; only a better
+        // champion out of reach needs the bin's list
+        const unsigned long long kb = best[nb];
+        const float s2 = __uint_as_float((uint32_t)(kb >> 32));
+        const int32_t tm2 = 0xFFFF - (int32_t)((kb >> 16) & 0xFFFF);
+        const int64_t th2 = t2 * bg.cw + (0xFFFF - (int64_t)(kb & 0xFFFF));
+        const int64_t tl2 = (int64_t)best_tl[nb];
+        if (!coinc_better(s2, tm2, th2, tl2, r.stat, a.tmpl, a.tick, tl)) continue;
+        int64_t d2 = pos_mod(th2 - a.tick + wrap / 2, wrap) - wrap / 2;
+        if (d2 < 0) d2 = -d2;
+        if (d2 <= bg.cw) return;
         for (uint64_t p = start[nb]; p < start[nb + 1]; ++p) {
             const RawCoinc o = raw[lists[p]];
             const hs_trigger oa = h[o.i];
