@@ -350,7 +350,12 @@ def main():
     if res_h is not None:
         out["hier_plain"] = {"value": round(full_ts / wall_h, 1), "ms_per_step": round(wall_h * 1e3, 3),
                              "followed_templates": [int(c) for c in res_h.followed]}
+    # Sec. V, Eq. (8) with this workload's counts (per detector) beside the measured ratio of
+    # matched-filter device time (event-timed passes of the two searches)
+    eq8 = search.speedup_eq8(1, args.fine, args.coarse, int(sum(res_m.followed)), fs, fs / cfg.decim, T)
+    out["cost_model"] = {"eq8_speedup": round(eq8, 3)}
     if flat:
+        out["cost_model"]["measured_mf_speedup"] = round(flat["res_t"].mf_ms / max(res_mt.mf_ms, 1e-9), 3)
         out["far"]["flat"] = far_summary(flat["res"])
         out["flat"] = {"value": round(flat["res"].template_seconds / flat["wall"], 1),
                        "ms_per_step": round(flat["wall"] * 1e3, 3)}

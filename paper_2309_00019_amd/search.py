@@ -134,6 +134,17 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
 YEAR = 365.25 * 86400.0
 
 
+def speedup_eq8(n_seg: int, n_flat: int, n_stage1: int, n_stage2: int, f_flat: float, f_coarse: float,
+                t_seg: float, gamma: float = 1.0) -> float:
+    """Sec. V, Eq. (8): matched-filter speed-up of the two-stage search over the flat one when one
+    template on one segment costs kappa N log N (N = f t_seg samples; kappa and the logarithm's
+    base cancel); n_stage2 counts (template, segment) applications, gamma the per-segment overhead."""
+    def cost(f):
+        m = f * t_seg
+        return m * np.log(m)
+    return float(n_seg * n_flat * cost(f_flat) / (n_seg * n_stage1 * cost(f_coarse) + n_stage2 * gamma * cost(f_flat)))
+
+
 def background_far(ctx, res: "SearchResult", cfg: SearchConfig):
     """Sec. IV: Eq. (7) fit of the background counts, hybrid FAR of every zero-lag coincidence
     (device float64 per record, -1 for background records, per second) and the statistic

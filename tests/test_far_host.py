@@ -31,3 +31,14 @@ def test_far_threshold_matches_oracle():
     yr = 365.25 * 86400.0
     for ifar in (yr, 10 * yr):
         assert abs(hs.hs_far_threshold(14.2, -1.7, 5.12e5, ifar) - F.ifar_threshold(14.2, -1.7, 5.12e5, ifar)) < 1e-12
+
+
+def test_package_eq8_matches_the_oracle_cost_model():
+    """The package's own Eq. (8) (used by the benchmark) against the oracle's pinned one."""
+    import oracle
+    from paper_2309_00019_amd import search
+    for args in ((1493, 428725, 85080, 6274846, 2048.0, 512.0, 512.0), (1, 30000, 1500, 10666, 2048.0, 512.0, 256.0)):
+        for gamma in (1.0, 3.0):
+            a = search.speedup_eq8(*args, gamma=gamma)
+            b = oracle.speedup_eq8(*args, gamma=gamma)
+            assert abs(a - b) <= 1e-12 * b
