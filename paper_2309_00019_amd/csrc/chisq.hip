@@ -55,6 +55,7 @@ __global__ void chisq_compact(const uint32_t *__restrict__ flag, const uint64_t 
 // Groups of at most CQ_GROUP consecutive active triggers of one template share each pass over
 // the template's band (active triggers are in trigger order, so a template's are contiguous).
 static constexpr int CQ_GROUP = 8;
+static constexpr int CQ_UNROLL = 2;
 
 __global__ void chisq_group_starts(const hs_trigger *trig, const uint32_t *__restrict__ act, int64_t n_act,
                                    uint32_t *__restrict__ start) {
@@ -74,11 +75,58 @@ __global__ void chisq_group_list(const uint32_t *__restrict__ start, const uint6
     if (a < n_act && start[a]) gfirst[off[a]] = (uint32_t)a;
 }
 
+// Bit pattern of lane 0's value in scalar registers (for values every lane computes alike).
+__device__ __forceinline__ double uniform_f64(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// P_j(w_j) = sum_{i < nb} q_i w_j^i for NG triggers at once by Horner's rule from the top term
+// down, q_i = d~ conj(w~) at bin k_f + 256 i.  CQ_UNROLL terms per trip, their loads issued
+// before the arithmetic; the trip count is rounded up at the top, where the extra terms are zeros
+// entering a zero polynomial (their loads are clamped to the last bin and discarded).
+template <typename ST, int NG>
+__device__ __forceinline__ void horner(const float2 *__restrict__ dspec, const typename ST::elem *__restrict__ spectra,
+                                       int64_t base, int64_t k_f, int64_t nb, const double *sr, const double *si,
+                                       double *hr, double *hi) {
+    const int64_t top = (nb + CQ_UNROLL - 1) / CQ_UNROLL * CQ_UNROLL;
+    for (int64_t jj = top - 1; jj >= 0; jj -= CQ_UNROLL) {
+        float2 q[CQ_UNROLL];
+#pragma unroll
+        for (int u = 0; u < CQ_UNROLL; ++u) {
+            const int64_t i = jj - u < nb ? jj - u : nb - 1;
+            const int64_t k = k_f + i * CQ_THREADS;
+            q[u] = cmulc(dspec[k], ST::load(spectra, base + k));
+        }
+#pragma unroll
+        for (int u = 0; u < CQ_UNROLL; ++u) {
+            const bool live = jj - u < nb;
+            const double qr = live ? (double)q[u].x : 0.0, qi = live ? (double)q[u].y : 0.0;
+#pragma unroll
+            for (int j = 0; j < NG; ++j) {
+                const double nr = fma(hr[j], sr[j], fma(-hi[j], si[j], qr));
+                hi[j] = fma(hr[j], si[j], fma(hi[j], sr[j], qi));
+                hr[j] = nr;
+            }
+        }
+    }
+}
+
 // z_l for one (bin l, group of active triggers of one template): sum over the bins of l of
 // q_k exp(+2 pi i k m / N), q_k = d~_k conj(w~_k) formed once per bin in float32 and shared by the
-// group's triggers; everything after it in float64.  Each thread owns the bins k0 + tid + 256 j;
-// per trigger its phasor starts from an exact float64 sincospi of (k m mod N) / N and advances by
-// the fixed step exp(2 pi i (256 m mod N) / N), so no twiddle table is read.
+// group's triggers; everything after it in float64.  With v = exp(2 pi i m / N) and b0 the first
+// bin, thread tid owns the bins b0 + tid + 256 i (i < nb) and
+//     z_l = v^b0 sum_tid v^tid P_tid(v^256),   P_tid(w) = sum_i q_i w^i.
+// Each thread evaluates its P by Horner's rule (one complex multiply-add per bin and trigger);
+// the sum over threads is a tree whose level s joins blocks of 2^s threads with the factor
+// v^(2^s) (shuffles inside a wavefront, then the four wavefronts through LDS), and v^b0 is applied
+// last.  Every power of v used is an exact float64 sincospi of (E m mod N) / N, computed once per
+// workgroup (one per lane), so no twiddle table is read; v^256 is the same in every lane and
+// lives in scalar registers.
+static constexpr int CQ_PH = 10;  // v^1, v^2, ..., v^128, v^256, v^b0
+
 template <typename ST>
 __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     const float2 *__restrict__ dspec, int64_t n, const typename ST::elem *__restrict__ spectra,
@@ -86,13 +134,16 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     const int32_t *__restrict__ khi, const int32_t *__restrict__ edges, int p, const hs_trigger *trig,
     const uint32_t *__restrict__ act, int64_t n_act, const uint32_t *__restrict__ gfirst, int64_t seg_t0,
     int64_t tps, double2 *__restrict__ zl) {
-    __shared__ double red[CQ_THREADS / 64][CQ_GROUP][2];
+    static_assert(CQ_THREADS == 256, "the tree below joins four wavefronts of 64 with v^64 and v^128");
+    constexpr int G = CQ_GROUP;
+    __shared__ double2 ph[G][CQ_PH];
+    __shared__ double2 red[CQ_THREADS / 64][G];
     const int64_t a0 = gfirst[blockIdx.x];
     const int l = blockIdx.y;
     const int tid = threadIdx.x;
     const int t = trig[act[a0]].tmpl;
     int g = 1;
-    while (g < CQ_GROUP && a0 + g < n_act && trig[act[a0 + g]].tmpl == t) ++g;
+    while (g < G && a0 + g < n_act && trig[act[a0 + g]].tmpl == t) ++g;
     const int32_t *e = edges + (int64_t)t * (p + 1);
     const int64_t base = offset[t] - k0[t];
     // every bin is clamped to the template's band, which lies inside [1, n/2 - 1]
@@ -100,57 +151,60 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     const int64_t band_hi = khi[t] < n / 2 - 1 ? khi[t] : n / 2 - 1;
     const int64_t b0 = e[l] > band_lo ? e[l] : band_lo;
     const int64_t b1 = e[l + 1] < band_hi + 1 ? e[l + 1] : band_hi + 1;
-    const uint64_t mask = (uint64_t)n - 1;
-    const double inv_half_n = 2.0 / (double)n;
-    const int64_t k_first = b0 + tid;
-    double ar[CQ_GROUP], ai[CQ_GROUP], wr[CQ_GROUP], wi[CQ_GROUP], sr[CQ_GROUP], si[CQ_GROUP];
-#pragma unroll
-    for (int j = 0; j < CQ_GROUP; ++j) {
-        ar[j] = ai[j] = 0.0;
-        wr[j] = 1.0;
-        wi[j] = sr[j] = si[j] = 0.0;
-        if (j < g && k_first < b1) {
-            const uint64_t m = (uint64_t)((trig[act[a0 + j]].tick - seg_t0) / tps);
-            sincospi((double)(((uint64_t)k_first * m) & mask) * inv_half_n, &wi[j], &wr[j]);
-            sincospi((double)(((uint64_t)CQ_THREADS * m) & mask) * inv_half_n, &si[j], &sr[j]);
-        }
+    if (tid < g * CQ_PH) {
+        const int j = tid / CQ_PH, s = tid - j * CQ_PH;
+        const uint64_t m = (uint64_t)((trig[act[a0 + j]].tick - seg_t0) / tps);
+        const uint64_t ex = s < 9 ? (uint64_t(1) << s) : (uint64_t)b0;
+        double sn, cs;
+        sincospi((double)((ex * m) & ((uint64_t)n - 1)) * (2.0 / (double)n), &sn, &cs);
+        ph[j][s] = double2{cs, sn};
     }
-    for (int64_t k = k_first; k < b1; k += CQ_THREADS) {
-        const float2 q = cmulc(dspec[k], ST::load(spectra, base + k));
-        const double qr = (double)q.x, qi = (double)q.y;
+    __syncthreads();
+    const int64_t k_f = b0 + tid;
+    const int64_t nb = k_f < b1 ? (b1 - 1 - k_f) / CQ_THREADS + 1 : 0;
+    double hr[G], hi[G], sr[G], si[G];
 #pragma unroll
-        for (int j = 0; j < CQ_GROUP; ++j) {
-            if (j < g) {
-                ar[j] += qr * wr[j] - qi * wi[j];
-                ai[j] += qr * wi[j] + qi * wr[j];
-                const double nr = wr[j] * sr[j] - wi[j] * si[j];
-                wi[j] = wr[j] * si[j] + wi[j] * sr[j];
-                wr[j] = nr;
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < CQ_GROUP; ++j) {
+    for (int j = 0; j < G; ++j) {
+        hr[j] = hi[j] = sr[j] = si[j] = 0.0;
         if (j < g) {
-            double x = ar[j], y = ai[j];
-            for (int o = 32; o > 0; o >>= 1) {
-                x += __shfl_down(x, o);
-                y += __shfl_down(y, o);
+            sr[j] = uniform_f64(ph[j][8].x);
+            si[j] = uniform_f64(ph[j][8].y);
+        }
+    }
+    switch (g) {  // a loop without per-trigger predicates for each group size
+    case 1: horner<ST, 1>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 2: horner<ST, 2>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 3: horner<ST, 3>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 4: horner<ST, 4>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 5: horner<ST, 5>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 6: horner<ST, 6>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    case 7: horner<ST, 7>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    default: horner<ST, 8>(dspec, spectra, base, k_f, nb, sr, si, hr, hi); break;
+    }
+    // tree inside the wavefront: after level s, lane L with L mod 2^(s+1) = 0 holds
+    // sum_{u < 2^(s+1)} v^u P_{L+u}; its partner block starts at L + 2^s
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        if (j < g) {
+            double x = hr[j], y = hi[j];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const double xd = __shfl_down(x, 1 << s), yd = __shfl_down(y, 1 << s);
+                const double2 v = ph[j][s];
+                x += v.x * xd - v.y * yd;
+                y += v.x * yd + v.y * xd;
             }
-            if ((tid & 63) == 0) {
-                red[tid >> 6][j][0] = x;
-                red[tid >> 6][j][1] = y;
-            }
+            if ((tid & 63) == 0) red[tid >> 6][j] = double2{x, y};
         }
     }
     __syncthreads();
     if (tid < g) {
-        double x = 0.0, y = 0.0;
-        for (int w = 0; w < CQ_THREADS / 64; ++w) {
-            x += red[w][tid][0];
-            y += red[w][tid][1];
-        }
-        zl[(a0 + tid) * p + l] = double2{x, y};
+        const double2 v64 = ph[tid][6], v128 = ph[tid][7], vb = ph[tid][9];
+        const double2 r0 = red[0][tid], r1 = red[1][tid], r2 = red[2][tid], r3 = red[3][tid];
+        const double ax = r0.x + (v64.x * r1.x - v64.y * r1.y), ay = r0.y + (v64.x * r1.y + v64.y * r1.x);
+        const double bx = r2.x + (v64.x * r3.x - v64.y * r3.y), by = r2.y + (v64.x * r3.y + v64.y * r3.x);
+        const double cx = ax + (v128.x * bx - v128.y * by), cy = ay + (v128.x * by + v128.y * bx);
+        zl[(a0 + tid) * p + l] = double2{vb.x * cx - vb.y * cy, vb.x * cy + vb.y * cx};
     }
 }
 
@@ -182,6 +236,17 @@ __global__ void chisq_finish(const double2 *__restrict__ zl, const uint32_t *__r
     hs_trigger o = tr;
     o.snr = (float)rw;
     trig_out[i] = o;
+}
+
+template <typename ST>
+static int launch_bin_sums(hs_ctx *ctx, dim3 gs, const float2 *d, int64_t n, const hs_bank *bank, int p,
+                           const hs_trigger *trig, const uint32_t *act, int64_t n_act, const uint32_t *gfirst,
+                           int64_t seg_t0, int64_t tps, double2 *zl) {
+    hipLaunchKernelGGL(chisq_bin_sums<ST>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
+                       static_cast<const typename ST::elem *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
+                       bank->k_hi, bank->chisq_edges, p, trig, act, n_act, gfirst, seg_t0, tps, zl);
+    HS_HIP(hipGetLastError());
+    return HS_OK;
 }
 
 }  // namespace hs
@@ -253,22 +318,18 @@ extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, con
     const float2 *d = static_cast<const float2 *>(spec);
     switch (bank->dtype) {
     case HS_F32:
-        hipLaunchKernelGGL(chisq_bin_sums<StoreF32>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
-                           static_cast<const float2 *>(bank->spectra), bank->offset, bank->k0, bank->k_lo, bank->k_hi,
-                           bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
+        HS_TRY((launch_bin_sums<StoreF32>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
+                                          ticks_per_sample, zl)));
         break;
     case HS_BF16:
-        hipLaunchKernelGGL(chisq_bin_sums<StoreBF16>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
-                           static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                           bank->k_hi, bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
+        HS_TRY((launch_bin_sums<StoreBF16>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
+                                           ticks_per_sample, zl)));
         break;
     default:
-        hipLaunchKernelGGL(chisq_bin_sums<StoreF16>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
-                           static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                           bank->k_hi, bank->chisq_edges, p, trig, act, (int64_t)n_act, gfirst, seg_t0, ticks_per_sample, zl);
+        HS_TRY((launch_bin_sums<StoreF16>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
+                                          ticks_per_sample, zl)));
         break;
     }
-    HS_HIP(hipGetLastError());
     hipLaunchKernelGGL(chisq_finish, dim3((unsigned)cdiv((int64_t)n_act, 256)), dim3(256), 0, ctx->stream, zl, act,
                        (int64_t)n_act, p, trig, bank->rho2_scale, chisq_out, trig_out, bins_out);
     HS_HIP(hipGetLastError());

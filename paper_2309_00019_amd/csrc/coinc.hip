@@ -16,9 +16,15 @@
 // (against their champions first, scanning a tile's members only when its better champion lies
 // out of reach).
 // Survivors are compacted in bin order, i.e. sorted by (slide, tick_h).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "hs_internal.h"
 
 namespace hs {
+
+static constexpr int CO_MAX_EDGES = 4096;
 
 struct RawCoinc {
     uint32_t i, j, k;
@@ -178,56 +184,97 @@ __device__ __forceinline__ bool coinc_better(float s2, int32_t tm2, int64_t th2,
     return tl2 < tl1;
 }
 
-__global__ void co_champion(const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h,
-                            const hs_trigger *__restrict__ l, BinGeom bg, int64_t wrap,
-                            const unsigned long long *__restrict__ best, const unsigned long long *__restrict__ best_tl,
-                            const uint64_t *__restrict__ start, const uint32_t *__restrict__ lists,
-                            uint32_t *__restrict__ flag, uint32_t *__restrict__ slot) {
+// Per coincidence: only the champion of its bin can survive; it checks the neighbouring tiles of
+// its slide.  A neighbour bin's champion is its best member in the same order, so if it is not
+// better no member is, and if it is better and within reach this one loses.  Only a better
+// champion out of reach leaves the bin's members to scan; those scans are done by the whole
+// wavefront, 64 members at a time, one pending scan after another (a glitch can put thousands
+// of same-slide pairs into one bin, too many for one lane).
+__global__ __launch_bounds__(256) void co_champion(
+    const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h, const hs_trigger *__restrict__ l,
+    BinGeom bg, int64_t wrap, const unsigned long long *__restrict__ best,
+    const unsigned long long *__restrict__ best_tl, const uint64_t *__restrict__ start,
+    const uint32_t *__restrict__ lists, uint32_t *__restrict__ flag, uint32_t *__restrict__ slot) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= P) return;
-    const RawCoinc r = raw[q];
-    const hs_trigger a = h[r.i];
-    const int64_t tl = l[r.j].tick;
-    int64_t tile;
-    const int64_t b = coinc_bin(r, a.tick, bg, &tile);
-    if (coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw) != best[b] || (unsigned long long)tl != best_tl[b]) return;
-    const int64_t nt = bg.n_tiles;
-    const int64_t slide0 = (int64_t)r.k * nt;
-    // neighbour tiles at circular offsets -2..2 (distinct, excluding this tile)
-    int64_t seen[4];
-    int ns = 0;
-    for (int dd = -2; dd <= 2; ++dd) {
-        if (dd == 0) continue;
-        const int64_t t2 = pos_mod(tile + dd, nt);
-        if (t2 == tile) continue;
-        bool dup = false;
-        for (int s = 0; s < ns; ++s) dup |= (seen[s] == t2);
-        if (dup) continue;
-        seen[ns++] = t2;
-        const int64_t nb = slide0 + t2;
-        if (start[nb] == start[nb + 1]) continue;
-        // the neighbour bin's champion is its best member in the same order: if it is not
-        // better, no member is; if it is better and within reach, this one loses; only a better
-        // champion out of reach needs the bin's list
-        const unsigned long long kb = best[nb];
-        const float s2 = __uint_as_float((uint32_t)(kb >> 32));
-        const int32_t tm2 = 0xFFFF - (int32_t)((kb >> 16) & 0xFFFF);
-        const int64_t th2 = t2 * bg.cw + (0xFFFF - (int64_t)(kb & 0xFFFF));
-        const int64_t tl2 = (int64_t)best_tl[nb];
-        if (!coinc_better(s2, tm2, th2, tl2, r.stat, a.tmpl, a.tick, tl)) continue;
-        int64_t d2 = pos_mod(th2 - a.tick + wrap / 2, wrap) - wrap / 2;
-        if (d2 < 0) d2 = -d2;
-        if (d2 <= bg.cw) return;
-        for (uint64_t p = start[nb]; p < start[nb + 1]; ++p) {
-            const RawCoinc o = raw[lists[p]];
-            const hs_trigger oa = h[o.i];
-            int64_t d = pos_mod(oa.tick - a.tick + wrap / 2, wrap) - wrap / 2;
-            if (d < 0) d = -d;
-            if (d <= bg.cw && coinc_better(o.stat, oa.tmpl, oa.tick, l[o.j].tick, r.stat, a.tmpl, a.tick, tl)) return;
+    const int lane = threadIdx.x & 63;
+    bool champ = false, lose = false;
+    RawCoinc r{0, 0, 0, 0.0f};
+    hs_trigger a{};
+    int64_t tl = 0, b = 0, tile = 0;
+    int64_t pend[4] = {0, 0, 0, 0};
+    int npend = 0;
+    if (q < P) {
+        r = raw[q];
+        a = h[r.i];
+        tl = l[r.j].tick;
+        b = coinc_bin(r, a.tick, bg, &tile);
+        champ = coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw) == best[b] && (unsigned long long)tl == best_tl[b];
+    }
+    if (champ) {
+        const int64_t nt = bg.n_tiles;
+        const int64_t slide0 = (int64_t)r.k * nt;
+        // neighbour tiles at circular offsets -2..2 (distinct, excluding this tile)
+        int64_t seen[4];
+        int ns = 0;
+        for (int dd = -2; dd <= 2 && !lose; ++dd) {
+            if (dd == 0) continue;
+            const int64_t t2 = pos_mod(tile + dd, nt);
+            if (t2 == tile) continue;
+            bool dup = false;
+            for (int u = 0; u < ns; ++u) dup |= (seen[u] == t2);
+            if (dup) continue;
+            seen[ns++] = t2;
+            const int64_t nb = slide0 + t2;
+            if (start[nb] == start[nb + 1]) continue;
+            const unsigned long long kb = best[nb];
+            const float s2 = __uint_as_float((uint32_t)(kb >> 32));
+            const int32_t tm2 = 0xFFFF - (int32_t)((kb >> 16) & 0xFFFF);
+            const int64_t th2 = t2 * bg.cw + (0xFFFF - (int64_t)(kb & 0xFFFF));
+            const int64_t tl2 = (int64_t)best_tl[nb];
+            if (!coinc_better(s2, tm2, th2, tl2, r.stat, a.tmpl, a.tick, tl)) continue;
+            int64_t d2 = pos_mod(th2 - a.tick + wrap / 2, wrap) - wrap / 2;
+            if (d2 < 0) d2 = -d2;
+            if (d2 <= bg.cw) {
+                lose = true;
+                break;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u == npend) pend[u] = nb;
+            ++npend;
         }
     }
-    flag[b] = 1u;
-    slot[b] = (uint32_t)q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        uint64_t want = __ballot(champ && !lose && u < npend);
+        while (want) {
+            const int src = __ffsll((unsigned long long)want) - 1;
+            want &= want - 1;
+            const int64_t nb = __shfl(pend[u], src);
+            const int64_t th = __shfl(a.tick, src);
+            const int64_t tls = __shfl(tl, src);
+            const float st = __shfl(r.stat, src);
+            const int32_t tm = __shfl(a.tmpl, src);
+            const uint64_t p0 = start[nb], p1 = start[nb + 1];
+            bool found = false;
+            for (uint64_t p = p0; p < p1; p += 64) {
+                if (p + lane < p1) {
+                    const RawCoinc o = raw[lists[p + lane]];
+                    const hs_trigger oa = h[o.i];
+                    int64_t d = pos_mod(oa.tick - th + wrap / 2, wrap) - wrap / 2;
+                    if (d < 0) d = -d;
+                    found = d <= bg.cw && coinc_better(o.stat, oa.tmpl, oa.tick, l[o.j].tick, st, tm, th, tls);
+                }
+                if (__ballot(found)) break;
+            }
+            const bool any = __ballot(found) != 0;  // every lane takes part in the vote
+            if (lane == src && any) lose = true;
+        }
+    }
+    if (champ && !lose) {
+        flag[b] = 1u;
+        slot[b] = (uint32_t)q;
+    }
 }
 
 __global__ void co_emit(const RawCoinc *__restrict__ raw, const hs_trigger *__restrict__ h,
@@ -252,23 +299,30 @@ __global__ void co_emit(const RawCoinc *__restrict__ raw, const hs_trigger *__re
     out[pos] = o;
 }
 
-// bg[e] = number of surviving coincidences with slide >= 1 and (double)stat >= e2[e]
+// hist[c] += number of surviving coincidences with slide >= 1 and exactly c of the ascending
+// thresholds e2s[0..n_e) at or below (double)stat (a binary search per survivor; workgroup
+// histograms in LDS).  The count at threshold i is then the sum of hist[c] over c > i.
 __global__ __launch_bounds__(256) void co_background(const RawCoinc *__restrict__ raw, int64_t n_tiles, int64_t bins,
                                                      const uint32_t *__restrict__ flag,
-                                                     const uint32_t *__restrict__ slot, const double *__restrict__ e2,
-                                                     unsigned long long *__restrict__ bgc) {
-    __shared__ unsigned long long sh[256];
-    const double x = e2[blockIdx.x];
-    unsigned long long c = 0;
-    for (int64_t b = n_tiles + threadIdx.x; b < bins; b += 256)
-        if (flag[b] && (double)raw[slot[b]].stat >= x) ++c;
-    sh[threadIdx.x] = c;
+                                                     const uint32_t *__restrict__ slot, const double *__restrict__ e2s,
+                                                     int n_e, unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t sh[CO_MAX_EDGES + 1];
+    for (int i = threadIdx.x; i <= n_e; i += 256) sh[i] = 0u;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
+    for (int64_t b = n_tiles + blockIdx.x * (int64_t)256 + threadIdx.x; b < bins; b += (int64_t)gridDim.x * 256) {
+        if (!flag[b]) continue;
+        const double x = (double)raw[slot[b]].stat;
+        int lo = 0, hi = n_e;  // e2s[< lo] <= x < e2s[>= hi]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (e2s[mid] <= x) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicAdd(&sh[lo], 1u);
     }
-    if (threadIdx.x == 0) bgc[blockIdx.x] = sh[0];
+    __syncthreads();
+    for (int i = threadIdx.x; i <= n_e; i += 256)
+        if (sh[i]) atomicAdd(&hist[i], (unsigned long long)sh[i]);
 }
 
 }  // namespace hs
@@ -288,6 +342,9 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     HS_REQUIRE(nh < (int64_t(1) << 31) && nl < (int64_t(1) << 31) && n_slides < (int64_t(1) << 31),
                "hs_timeslide_coinc: input too large");
     HS_REQUIRE(n_edges == 0 || (edges && bg_counts), "hs_timeslide_coinc: null edges/bg_counts");
+    HS_REQUIRE(n_edges <= CO_MAX_EDGES, "hs_timeslide_coinc: at most %d edges (got %d)", CO_MAX_EDGES, (int)n_edges);
+    for (int e = 0; e < n_edges; ++e)
+        HS_REQUIRE(!std::isnan(edges[e]), "hs_timeslide_coinc: edges[%d] is NaN", e);
     *n_out = 0;
     for (int e = 0; e < n_edges; ++e) bg_counts[e] = 0;
     if (nh == 0 || nl == 0) return HS_OK;
@@ -368,7 +425,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         cv.add(&tmp2, scan_tmp_elems(bins > (int64_t)P ? bins : (int64_t)P));
         cv.add(&lists, P);
         cv.add(&e2, n_edges > 0 ? n_edges : 1);
-        cv.add(&bgc, n_edges > 0 ? n_edges : 1);
+        cv.add(&bgc, n_edges + 1);
         HS_TRY(cv.commit(ctx));
     }
     hipLaunchKernelGGL(co_pair_write, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l, n_tmpl, g,
@@ -393,15 +450,30 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
                        boff, out, cap);
     HS_HIP(hipGetLastError());
     if (n_edges > 0) {
+        // thresholds in ascending order (ties keep their order), counted in one pass over the bins
         std::vector<double> he2(n_edges);
-        for (int e = 0; e < n_edges; ++e) he2[e] = (double)edges[e] * (double)edges[e];
-        HS_HIP(hipMemcpyAsync(e2, he2.data(), n_edges * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        hipLaunchKernelGGL(co_background, dim3((unsigned)n_edges), dim3(256), 0, ctx->stream, raw, n_tiles, bins, flag,
-                           slot, e2, bgc);
+        std::vector<int> order(n_edges);
+        for (int e = 0; e < n_edges; ++e) {
+            he2[e] = (double)edges[e] * (double)edges[e];
+            order[e] = e;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return he2[x] < he2[y]; });
+        std::vector<double> hs2(n_edges);
+        for (int i = 0; i < n_edges; ++i) hs2[i] = he2[order[i]];
+        HS_HIP(hipMemcpyAsync(e2, hs2.data(), n_edges * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(bgc), n_edges + 1, 0));
+        const int64_t span = bins - n_tiles;
+        const unsigned gb = (unsigned)(span <= 0 ? 1 : (cdiv(span, 256) < 1024 ? cdiv(span, 256) : 1024));
+        hipLaunchKernelGGL(co_background, dim3(gb), dim3(256), 0, ctx->stream, raw, n_tiles, bins, flag, slot, e2,
+                           (int)n_edges, bgc);
         HS_HIP(hipGetLastError());
-        std::vector<unsigned long long> hb(n_edges);
-        HS_TRY(read_back(ctx, bgc, hb.data(), n_edges * sizeof(unsigned long long)));
-        for (int e = 0; e < n_edges; ++e) bg_counts[e] = (int64_t)hb[e];
+        std::vector<unsigned long long> hh(n_edges + 1);
+        HS_TRY(read_back(ctx, bgc, hh.data(), (n_edges + 1) * sizeof(unsigned long long)));
+        unsigned long long above = 0;
+        for (int i = n_edges - 1; i >= 0; --i) {
+            above += hh[i + 1];
+            bg_counts[order[i]] = (int64_t)above;
+        }
     }
     uint64_t total = 0;
     HS_TRY(read_back(ctx, boff + bins, &total, sizeof(total)));

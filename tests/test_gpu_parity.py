@@ -402,6 +402,41 @@ def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind):
     assert np.any(chi > 3.0)  # the glitches are flagged
 
 
+def test_chisq_every_group_size_matches_oracle(ctx):
+    """Triggers placed by hand, 1 to 10 per template at random samples (the first and last sample
+    among them), so the band sums see every group size and a template split over two groups."""
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("chisq group sizes")
+    n, fs, f_low = 2 ** 15, 2048.0, 20.0
+    bank = _bank_for("tau", n, fs, f_low, count=10, seed=21)
+    s = _strain(21, 0, n, fs, f_low, glitch_rate=0.5)
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    rng = np.random.default_rng(21)
+    tps, t0 = 25, 5000
+    rows = []
+    for t in range(bank.n_tmpl):
+        ms = np.sort(rng.choice(n, t + 1, replace=False))
+        if t == bank.n_tmpl - 1:
+            ms[0], ms[-1] = 0, n - 1
+        rows += [(0, t, t0 + int(m) * tps, 6.0, 0.0) for m in ms]
+    rec = np.array(rows, dtype=hs.TRIGGER)
+    trig = hs.to_device_records(rec, ctx.device)
+    chi, rw, bins = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=5.0, bins=True)
+    chi, bins, rw = chi.cpu().numpy(), bins.cpu().numpy(), hs.as_records(rw, hs.TRIGGER)
+    otr = oracle.pipeline.reweight_triggers({k: rec[k] for k in ("tmpl", "tick", "snr")}, oracle.strain_fft(s, fs),
+                                            psd, n, fs, f_low, bank, 8, 5.0, tps, t0)
+    for i in range(len(rec)):
+        c_ref = otr["chisq"][i]
+        assert abs(chi[i] - c_ref) <= 1e-3 * (1.0 + c_ref), (i, chi[i], c_ref)
+        assert np.all(np.abs(bins[i] - otr["bins"][i]) <= 1e-3 * (1.0 + 14.0 * c_ref)), (i, bins[i], otr["bins"][i])
+        assert abs(rw["snr"][i] / otr["snr"][i] - 1.0) < 2e-4, (i, rw["snr"][i], otr["snr"][i])
+    assert np.any(otr["chisq"] > 2.0) and np.any(otr["chisq"] < 1.0)
+
+
 def test_exact_capacity_holds_unevenly_spread_candidates(ctx):
     """Candidates concentrated in time (a loud glitch, two templates) must fit a capacity equal
     to their count: the striped lists spill instead of overflowing."""
