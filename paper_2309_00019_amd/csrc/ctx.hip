@@ -79,11 +79,19 @@ static void host_twiddles(int log2len, std::vector<long double> &re, std::vector
     }
 }
 
-void host_cos_f64(int log2len, std::vector<double> &out) {
-    std::vector<long double> re, im;
-    host_twiddles(log2len, re, im);
-    out.resize(re.size());
-    for (size_t j = 0; j < re.size(); ++j) out[j] = (double)re[j];
+double hann_sumsq(hs_ctx *ctx, int log2len) {
+    Twiddles &t = ctx->tw[log2len];
+    if (t.hann_sumsq < 0.0) {
+        std::vector<long double> re, im;
+        host_twiddles(log2len, re, im);
+        double acc = 0.0;
+        for (size_t j = 0; j < re.size(); ++j) {
+            const double w = 0.5 - 0.5 * (double)re[j];
+            acc += w * w;
+        }
+        t.hann_sumsq = acc;
+    }
+    return t.hann_sumsq;
 }
 
 int twiddles_f32(hs_ctx *ctx, int log2len, const float2 **out) {

@@ -45,6 +45,7 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Twiddles {
     void *f32 = nullptr;  // float2 [len]
     void *f64 = nullptr;  // double2 [len]
+    double hann_sumsq = -1.0;  // sum of squared periodic Hann weights of length len (set on first use)
 };
 
 }  // namespace hs
@@ -76,8 +77,9 @@ int pinned_reserve(hs_ctx *ctx, size_t bytes);
 // Device twiddle table exp(+2 pi i j / 2^log2len) in float32 or float64 (built on first use).
 int twiddles_f32(hs_ctx *ctx, int log2len, const float2 **out);
 int twiddles_f64(hs_ctx *ctx, int log2len, const double2 **out);
-// Host copy of the real parts of the float64 table (identical rounding).
-void host_cos_f64(int log2len, std::vector<double> &out);
+// Sum over j < 2^log2len of (0.5 - 0.5 cos(2 pi j / len))^2 from the same float64 cosines as the
+// float64 twiddle table, computed once per length and kept in the context.
+double hann_sumsq(hs_ctx *ctx, int log2len);
 
 // Carves aligned sub-buffers out of the arena for one call.
 struct Carver {

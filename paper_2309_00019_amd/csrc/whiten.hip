@@ -102,13 +102,7 @@ int hs_welch_psd(hs_ctx *ctx, const float *strain, int64_t n, double fs, int64_t
     const double2 *tw;
     HS_TRY(twiddles_f64(ctx, lg, &tw));
     // sum of squared window values, from the same float64 values the kernel reads
-    std::vector<double> cosv;
-    host_cos_f64(lg, cosv);
-    double wss = 0.0;
-    for (int64_t i = 0; i < L; ++i) {
-        const double w = 0.5 - 0.5 * cosv[i];
-        wss += w * w;
-    }
+    const double wss = hann_sumsq(ctx, lg);
     double2 *a, *b;
     double *pw;
     Carver cv;
