@@ -78,8 +78,8 @@ TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
 
 def measured_traffic_per_template():
     """HBM bytes per template of the matched filter recorded in the committed rocprofv3 counter
-    summary, or None when mf.hip has changed since the counters were taken (source hash recorded
-    there)."""
+    summary (default workload), or None when mf.hip has changed since the counters were taken
+    (source hash recorded there)."""
     import hashlib
     import re
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2309_00019_amd", "csrc", "mf.hip")
@@ -313,7 +313,8 @@ def main():
     mf_b = mf_bytes(src.mf_units, hs)
     launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel(), ctx)) for n_, ids, _ in src.mf_units)
     achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
-    per_tmpl = measured_traffic_per_template()
+    # the counters were taken on the default workload (fine bank at 2^19 samples, float32 storage)
+    per_tmpl = measured_traffic_per_template() if (n == 2 ** 19 and args.dtype == "f32") else None
     n_tmpl_mf = sum(ids.numel() for _, ids, _ in src.mf_units)
     traffic = None if per_tmpl is None else int(per_tmpl * n_tmpl_mf / max(1, launches))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

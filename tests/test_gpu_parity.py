@@ -258,6 +258,41 @@ def test_timeslide_coinc_exact_on_identical_inputs(ctx, seed, wrap, K, step, win
     assert np.array_equal(bg, ref["bg_counts"])
 
 
+def test_timeslide_coinc_exact_on_crowded_bins(ctx):
+    """A glitch-like crowd: thousands of templates coincide within a few clustering tiles of the
+    same slides, so bins hold hundreds of pairs and champions must scan neighbour bins whose
+    better champion lies out of reach; the edges are unsorted and repeat a value."""
+    from paper_2309_00019_amd import hs
+    _say("coinc crowded bins")
+    g = np.random.default_rng(77)
+    n_tmpl, wrap, K, step, window, cw = 3000, 2_000_000, 3, 500_000, 200, 10_000
+    crowd = g.random(n_tmpl) < 0.8
+    th = np.where(crowd, g.integers(100_000, 160_000, n_tmpl), g.integers(0, wrap, n_tmpl)).astype(np.int64)
+    k = g.integers(0, K + 1, n_tmpl)
+    tl = (th - k * step + g.integers(-window, window + 1, n_tmpl)) % wrap
+    snr_h = np.round(g.uniform(5.0, 30.0, n_tmpl), 1).astype(np.float32)   # rounded: stat ties
+    snr_l = np.round(g.uniform(5.0, 30.0, n_tmpl), 1).astype(np.float32)
+
+    def rec(tick, snr):
+        r = np.zeros(n_tmpl, dtype=hs.TRIGGER)
+        r["tmpl"], r["tick"], r["snr"] = np.arange(n_tmpl), tick, snr
+        return r
+    h, l = rec(th, snr_h), rec(tl, snr_l)
+    edges = np.array([9.0, 5.0, 30.0, 20.0, 20.0, 25.0, 8.0, 35.0, 15.0, 50.0], np.float32)
+    out, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(h, ctx.device), hs.to_device_records(l, ctx.device),
+                                    n_tmpl, K, step, window, wrap, cw, edges)
+    got = hs.as_records(out, hs.COINC)
+    ref = oracle.timeslide_coinc(dict(tmpl=h["tmpl"], tick=h["tick"], snr=h["snr"]),
+                                 dict(tmpl=l["tmpl"], tick=l["tick"], snr=l["snr"]),
+                                 K, step, window, wrap, cw, edges, 51200)
+    c = ref["coincs"]
+    assert len(got) == len(c["slide"]) > 0
+    for f in ("slide", "tmpl", "tick_h", "tick_l"):
+        assert np.array_equal(got[f], np.asarray(c[f]).astype(got[f].dtype)), f
+    assert np.array_equal(got["stat"], c["stat"])
+    assert np.array_equal(bg, ref["bg_counts"]) and bg[4] == bg[3] and bg[9] == 0
+
+
 # ------------------------------------------------------------------------------------------
 # a5: follow-up (identical inputs -> exact)
 # ------------------------------------------------------------------------------------------
