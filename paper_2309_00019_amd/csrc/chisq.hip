@@ -288,8 +288,7 @@ extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, con
     HS_HIP(hipGetLastError());
     uint64_t n_act = 0;
     int32_t hbad = 0;
-    HS_TRY(read_back(ctx, off + n_trig, &n_act, sizeof(n_act)));
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_TRY(read_back2(ctx, off + n_trig, &n_act, sizeof(n_act), bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "hs_chisq: trigger template outside the bank or tick outside this segment (code %d)", hbad);
     if (n_act == 0) return HS_OK;
     double2 *zl;

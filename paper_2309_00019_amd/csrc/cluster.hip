@@ -148,8 +148,7 @@ extern "C" int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_
     HS_HIP(hipGetLastError());
     uint64_t total = 0;
     int32_t hbad = 0;
-    HS_TRY(read_back(ctx, off + bins, &total, sizeof(total)));
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_TRY(read_back2(ctx, off + bins, &total, sizeof(total), bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "hs_cluster_triggers: candidate with tpos outside [0, n_ids) or m outside [0, n)");
     *n_out = (int64_t)total;
     if ((int64_t)total > cap)

@@ -388,8 +388,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     HS_TRY(exclusive_scan_u32(ctx, pc, nh, poff, tmp1));
     uint64_t P = 0;
     int32_t hbad = 0;
-    HS_TRY(read_back(ctx, poff + nh, &P, sizeof(P)));
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_TRY(read_back2(ctx, poff + nh, &P, sizeof(P), bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "hs_timeslide_coinc: trigger with tmpl outside [0, n_tmpl) or tick outside [0, wrap)");
     if (P == 0) return HS_OK;
     HS_REQUIRE(P < (uint64_t(1) << 32), "hs_timeslide_coinc: %llu coincident pairs exceed 2^32",
@@ -449,6 +448,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     hipLaunchKernelGGL(co_emit, dim3((unsigned)cdiv(bins, 256)), dim3(256), 0, ctx->stream, raw, h, l, bins, flag, slot,
                        boff, out, cap);
     HS_HIP(hipGetLastError());
+    uint64_t total = 0;
     if (n_edges > 0) {
         // thresholds in ascending order (ties keep their order), counted in one pass over the bins
         std::vector<double> he2(n_edges);
@@ -468,15 +468,16 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
                            (int)n_edges, bgc);
         HS_HIP(hipGetLastError());
         std::vector<unsigned long long> hh(n_edges + 1);
-        HS_TRY(read_back(ctx, bgc, hh.data(), (n_edges + 1) * sizeof(unsigned long long)));
+        HS_TRY(read_back2(ctx, bgc, hh.data(), (n_edges + 1) * sizeof(unsigned long long), boff + bins, &total,
+                          sizeof(total)));
         unsigned long long above = 0;
         for (int i = n_edges - 1; i >= 0; --i) {
             above += hh[i + 1];
             bg_counts[order[i]] = (int64_t)above;
         }
+    } else {
+        HS_TRY(read_back(ctx, boff + bins, &total, sizeof(total)));
     }
-    uint64_t total = 0;
-    HS_TRY(read_back(ctx, boff + bins, &total, sizeof(total)));
     *n_out = (int64_t)total;
     if ((int64_t)total > cap)
         return set_error(HS_EOVERFLOW, "hs_timeslide_coinc: %llu coincidences exceed capacity %lld",

@@ -66,6 +66,19 @@ int read_back(hs_ctx *ctx, const void *dev, void *host, size_t bytes) {
     return HS_OK;
 }
 
+int read_back2(hs_ctx *ctx, const void *dev0, void *host0, size_t bytes0, const void *dev1, void *host1,
+               size_t bytes1) {
+    const size_t o1 = (bytes0 + 15) & ~size_t(15);
+    HS_TRY(pinned_reserve(ctx, o1 + bytes1));
+    char *pin = static_cast<char *>(ctx->pinned);
+    HS_HIP(hipMemcpyAsync(pin, dev0, bytes0, hipMemcpyDeviceToHost, ctx->stream));
+    HS_HIP(hipMemcpyAsync(pin + o1, dev1, bytes1, hipMemcpyDeviceToHost, ctx->stream));
+    HS_HIP(hipStreamSynchronize(ctx->stream));
+    std::memcpy(host0, pin, bytes0);
+    std::memcpy(host1, pin + o1, bytes1);
+    return HS_OK;
+}
+
 // exp(+2 pi i j / len) evaluated in extended precision on the host and rounded once.
 static void host_twiddles(int log2len, std::vector<long double> &re, std::vector<long double> &im) {
     const int64_t len = int64_t(1) << log2len;

@@ -127,8 +127,7 @@ static int followup_impl(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_
     HS_HIP(hipGetLastError());
     uint64_t n_sel = 0;
     int32_t hbad = 0;
-    HS_TRY(read_back(ctx, soff + n_c, &n_sel, sizeof(n_sel)));
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_TRY(read_back2(ctx, soff + n_c, &n_sel, sizeof(n_sel), bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "hs_followup: followed coincidence with tmpl outside [0, n_coarse)");
     if (n_sel > 0) {
         const int64_t work = (int64_t)n_sel * n_fine;

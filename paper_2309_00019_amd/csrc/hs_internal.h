@@ -112,6 +112,9 @@ int fill_u32(hs_ctx *ctx, uint32_t *p, int64_t n, uint32_t v);
 int fill_u64(hs_ctx *ctx, uint64_t *p, int64_t n, uint64_t v);
 // Copy a small device value back to the host and synchronise.
 int read_back(hs_ctx *ctx, const void *dev, void *host, size_t bytes);
+// Two small device values back to the host with one synchronisation.
+int read_back2(hs_ctx *ctx, const void *dev0, void *host0, size_t bytes0, const void *dev1, void *host1,
+               size_t bytes1);
 
 // Batched complex FFT of `batch` contiguous sequences of length 2^log2len, Stockham,
 // in global memory.  sign = -1 forward, +1 inverse (unnormalised).  The result lands in
