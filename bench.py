@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--chunk", type=int, default=2048, help="templates generated per host chunk")
+    ap.add_argument("--batch-mb", type=int, default=0,
+                    help="matched-filter intermediate budget in MB; 0 = measure it in set-up (autotuner)")
     ap.add_argument("--only", choices=["both", "hier", "flat"], default="both",
                     help="restrict the run (profiling): hier = hierarchical + proposer only")
     ap.add_argument("--calib-copy", action="store_true",
@@ -189,7 +191,11 @@ def main():
     # schedule of the matched filter, measured on every 10th fine template and the background data
     spec_tune = hs.hs_whiten(ctx, strain_h, fs, f_low, psd_h)
     tune_ids = torch.arange(0, args.fine, 10, dtype=torch.int32, device=dev)
-    best_mb, tune_table = autotune.tune_mf_batch(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
+    if args.batch_mb > 0:           # fixed schedule (counter runs, where the tracer distorts timing)
+        hs.hs_set_mf_batch_bytes(ctx, args.batch_mb << 20)
+        best_mb, tune_table = args.batch_mb, {}
+    else:
+        best_mb, tune_table = autotune.tune_mf_batch(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
     del spec_tune
     torch.cuda.synchronize()
     log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s; proposer P = {prop.p_cum}; "

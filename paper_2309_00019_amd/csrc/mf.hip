@@ -91,14 +91,21 @@ __global__ __launch_bounds__(256, 4) void mf_pass_a(
     const int64_t base = offset[t] - k0[t];
     const int lo = klo[t], hi = khi[t];
 
-    float2 x[16];
+    // All 32 band loads are issued before any product uses them: a use right after each
+    // band-tested load would make the wavefront wait for every row in turn.
+    float2 dd[16], tt[16], x[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int k = k1 + N1 * (l + 16 * j);
-        float2 v = float2{0.0f, 0.0f};
-        if (k >= lo && k <= hi) v = cmulc(dspec[k], ST::load(spectra, base + k));
-        x[j] = v;
+        dd[j] = float2{0.0f, 0.0f};
+        tt[j] = float2{0.0f, 0.0f};
+        if (k >= lo && k <= hi) {
+            dd[j] = dspec[k];
+            tt[j] = ST::load(spectra, base + k);
+        }
     }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = cmulc(dd[j], tt[j]);
     float2 *Yt = Y + (size_t)tb * 512 * (size_t)N1;
     // Twiddles: W_512^{k2} = W_512^l W_32^j; the W_32^j are compile-time constants applied
     // before the radix-16 DFT over j, and the common factor W_512^l is merged after it with
