@@ -53,7 +53,9 @@ def parse():
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--chunk", type=int, default=2048, help="templates generated per host chunk")
     ap.add_argument("--batch-mb", type=int, default=0,
-                    help="matched-filter intermediate budget in MB; 0 = measure it in set-up (autotuner)")
+                    help="matched-filter intermediate budget in MB; 0 = measure it and the tile in set-up (autotuner)")
+    ap.add_argument("--tile", type=int, default=128, choices=[64, 128, 256],
+                    help="pass-B threads per workgroup when --batch-mb fixes the schedule")
     ap.add_argument("--only", choices=["both", "hier", "flat"], default="both",
                     help="restrict the run (profiling): hier = hierarchical + proposer only")
     ap.add_argument("--calib-copy", action="store_true",
@@ -193,9 +195,11 @@ def main():
     tune_ids = torch.arange(0, args.fine, 10, dtype=torch.int32, device=dev)
     if args.batch_mb > 0:           # fixed schedule (counter runs, where the tracer distorts timing)
         hs.hs_set_mf_batch_bytes(ctx, args.batch_mb << 20)
-        best_mb, tune_table = args.batch_mb, {}
+        hs.hs_set_mf_tile(ctx, args.tile)
+        sched = {"batch_mb": args.batch_mb, "tile": args.tile, "budgets": {}, "tiles": {}}
     else:
-        best_mb, tune_table = autotune.tune_mf_batch(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
+        sched = autotune.tune_mf_schedule(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
+    best_mb, tune_table = sched["batch_mb"], sched["budgets"]
     del spec_tune
     torch.cuda.synchronize()
     log(f"[setup] done in {time.perf_counter() - t_setup:.1f} s; proposer P = {prop.p_cum}; "
@@ -350,6 +354,7 @@ def main():
                    "followed_templates": [int(c) for c in res_m.followed],
                    "proposer_p_cum": prop.p_cum,
                    "mf_batch_mb": best_mb, "mf_autotune_us_per_template": tune_table,
+                   "mf_tile_threads": sched["tile"], "mf_autotune_tile_us_per_template": sched["tiles"],
                    "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }

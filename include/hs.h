@@ -111,6 +111,14 @@ int hs_abi_version(void);
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes);
 int64_t hs_get_mf_batch_bytes(const hs_ctx *ctx);
 
+/* Matched-filter tile: threads per pass-B workgroup, 64, 128 (default) or 256;
+ * a workgroup transforms threads / (N1/16) rows of N1 = n/512 points (widened
+ * to one row when N1/16 exceeds it).  Results do not depend on it; set by the
+ * autotuner.  HS_EINVAL for other values.  hs_get_mf_tile returns the current
+ * value (0 for a NULL context). */
+int hs_set_mf_tile(hs_ctx *ctx, int32_t pass_b_threads);
+int32_t hs_get_mf_tile(const hs_ctx *ctx);
+
 /*
  * One-sided Welch PSD (the weight S_n of Eq. (2); the paper does not say how
  * it is estimated).  Segments of seg_len samples every seg_len/2 samples,

@@ -2,37 +2,59 @@
 
 The two-pass filter stages a batch of templates' N-point intermediates between pass A and
 pass B.  Small batches leave the GPU under-filled at the kernel boundaries; large ones push the
-intermediate out of the 256 MB Infinity Cache before pass B reads it back.  The best budget
-depends on N, the bank's band lengths and the candidate volume, so it is measured: the filter
-runs on a sample of the real bank and data for each candidate budget (device time from events
-on the library's stream) and the fastest is set on the context.
+intermediate out of the 256 MB Infinity Cache before pass B reads it back.  Pass B's tile (the
+rows of the intermediate one workgroup transforms) trades LDS per workgroup against the number
+of workgroups.  The best setting depends on N, the bank's band lengths and the candidate
+volume, so it is measured: the filter runs on a sample of the real bank and data for each
+candidate (device time from events on the library's stream), first over the batch budgets at
+the default tile, then over the tiles at the best budget, and the fastest is set on the context.
+Neither knob changes the results (same candidates, same values).
 """
-import numpy as np
 import torch
 
 from . import hs
 
 BUDGETS_MB = (64, 96, 128, 160, 192, 256)
+TILES = (64, 128, 256)          # pass-B threads per workgroup
+
+
+def _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps):
+    hs.hs_matched_filter(ctx, spec, n, fs, bank, tmpl_ids, thr)          # warm-up (scratch growth)
+    best = float("inf")
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(ctx.stream)
+        hs.hs_matched_filter(ctx, spec, n, fs, bank, tmpl_ids, thr)
+        e.record(ctx.stream)
+        e.synchronize()
+        best = min(best, s.elapsed_time(e) * 1e3 / tmpl_ids.numel())
+    return round(best, 4)
 
 
 def tune_mf_batch(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, thr: float, budgets_mb=BUDGETS_MB,
                   reps: int = 3):
-    """Times hs_matched_filter over tmpl_ids for each budget, sets the fastest on ctx and returns
-    (best_mb, {mb: microseconds per template})."""
+    """Times hs_matched_filter over tmpl_ids for each budget (at the context's tile), sets the
+    fastest on ctx and returns (best_mb, {mb: microseconds per template})."""
     table = {}
     for mb in budgets_mb:
         hs.hs_set_mf_batch_bytes(ctx, int(mb) << 20)
-        hs.hs_matched_filter(ctx, spec, n, fs, bank, tmpl_ids, thr)          # warm-up (scratch growth)
-        best = float("inf")
-        for _ in range(reps):
-            s = torch.cuda.Event(enable_timing=True)
-            e = torch.cuda.Event(enable_timing=True)
-            s.record(ctx.stream)
-            hs.hs_matched_filter(ctx, spec, n, fs, bank, tmpl_ids, thr)
-            e.record(ctx.stream)
-            e.synchronize()
-            best = min(best, s.elapsed_time(e) * 1e3 / tmpl_ids.numel())
-        table[int(mb)] = round(best, 4)
+        table[int(mb)] = _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps)
     best_mb = min(table, key=table.get)
     hs.hs_set_mf_batch_bytes(ctx, best_mb << 20)
     return best_mb, table
+
+
+def tune_mf_schedule(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, thr: float, budgets_mb=BUDGETS_MB,
+                     tiles=TILES, reps: int = 3):
+    """Batch budget, then pass-B tile; sets both on ctx and returns
+    {"batch_mb", "tile", "budgets": {mb: us/template}, "tiles": {threads: us/template}}."""
+    hs.hs_set_mf_tile(ctx, 128)
+    best_mb, budgets = tune_mf_batch(ctx, spec, n, fs, bank, tmpl_ids, thr, budgets_mb, reps)
+    table = {}
+    for t in tiles:
+        hs.hs_set_mf_tile(ctx, int(t))
+        table[int(t)] = budgets[best_mb] if t == 128 else _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps)
+    best_t = min(table, key=table.get)
+    hs.hs_set_mf_tile(ctx, best_t)
+    return {"batch_mb": best_mb, "tile": best_t, "budgets": budgets, "tiles": table}

@@ -347,7 +347,7 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 4; }
+int hs_abi_version(void) { return 5; }
 
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
     HS_REQUIRE(ctx, "hs_set_mf_batch_bytes: null context");
@@ -358,6 +358,16 @@ int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
 }
 
 int64_t hs_get_mf_batch_bytes(const hs_ctx *ctx) { return ctx ? (int64_t)ctx->mf_batch_bytes : 0; }
+
+int hs_set_mf_tile(hs_ctx *ctx, int32_t pass_b_threads) {
+    HS_REQUIRE(ctx, "hs_set_mf_tile: null context");
+    HS_REQUIRE(pass_b_threads == 64 || pass_b_threads == 128 || pass_b_threads == 256,
+               "hs_set_mf_tile: pass-B workgroup of %d threads (64, 128 or 256)", (int)pass_b_threads);
+    ctx->mf_pb_threads = pass_b_threads;
+    return HS_OK;
+}
+
+int32_t hs_get_mf_tile(const hs_ctx *ctx) { return ctx ? ctx->mf_pb_threads : 0; }
 
 int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     if (!ctx) return hs::set_error(HS_EINVAL, "hs_create: ctx is NULL");

@@ -66,6 +66,7 @@ struct hs_ctx {
     std::map<int, hs::Twiddles> tw;
     // Matched-filter batch budget for the pass-A/pass-B intermediate (bytes).
     size_t mf_batch_bytes = size_t(128) << 20;
+    int mf_pb_threads = 128;  // matched-filter pass-B workgroup size (64, 128 or 256)
 };
 
 namespace hs {

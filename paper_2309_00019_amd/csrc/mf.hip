@@ -28,7 +28,6 @@
 namespace hs {
 
 static constexpr int PA_LDS_LSTRIDE = 16 * 16 + 16;  // float2 per l-block (padded by 16)
-static constexpr int PB_THREADS = 128;                // pass-B workgroup size
 static constexpr int MF_STRIPES = 64;                 // candidate lists (power of two)
 
 // Candidate lists: MF_STRIPES lists of stripe_cap records followed by one spill list of
@@ -227,15 +226,18 @@ __device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int 
     }
 }
 
-template <int N1, bool WRITE_Z>
-__global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
+// PBT threads per workgroup (64, 128 or 256; at least one row of N1/16 lanes): the pass-B tile,
+// PBT / (N1/16) rows per workgroup.  The tile is chosen per context (hs_set_mf_tile).
+template <int N1, int PBT, bool WRITE_Z>
+__global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
                                                  const int32_t *__restrict__ ids, int32_t id0, float thr2,
                                                  const float2 *__restrict__ twN1, const int32_t *__restrict__ bad,
                                                  hs_candidate *__restrict__ cand,
                                                  unsigned long long *__restrict__ counter, int64_t cap,
                                                  int64_t spill_cap, float2 *__restrict__ zout) {
     constexpr int LPR = N1 / 16;    // lanes per row
-    constexpr int RPB = PB_THREADS / LPR;  // rows per block
+    static_assert(PBT % LPR == 0 && PBT >= LPR && PBT <= 256, "pass-B tile: whole rows, at most 256 threads");
+    constexpr int RPB = PBT / LPR;  // rows per block
     constexpr int R2 = PassBPlan<N1>::R2, R3 = PassBPlan<N1>::R3;
     constexpr int ROW = lds_row_len<N1>();
     constexpr int LDS_N = N1 > 16 ? RPB * ROW : 1024;
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
         }
         __syncthreads();
         const unsigned long long first_over = s_base > (unsigned long long)cap ? s_base : (unsigned long long)cap;
-        for (unsigned int i = threadIdx.x; i < k; i += PB_THREADS) {
+        for (unsigned int i = threadIdx.x; i < k; i += PBT) {
             const unsigned long long idx = s_base + i;
             if (idx < (unsigned long long)cap) {
                 cand[(size_t)stripe * cap + idx] = stage[i];
@@ -345,14 +347,43 @@ __global__ __launch_bounds__(PB_THREADS) void mf_pass_b(const float2 *__restrict
     }
 }
 
+// Pass-B threads per workgroup for rows of N1 points: the context's tile, widened to one row.
+static int pass_b_threads(const hs_ctx *ctx, int N1) {
+    const int t = ctx->mf_pb_threads;
+    return t < N1 / 16 ? N1 / 16 : t;
+}
+
+template <int N1, bool WRITE_Z>
+static void launch_pass_b_n(hs_ctx *ctx, int pbt, int tb, const float2 *Y, const float *r2s, const int32_t *ids,
+                            int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
+                            unsigned long long *counter, int64_t cap, int64_t spill_cap, float2 *zout) {
+    constexpr int LPR = N1 / 16;
+    const dim3 grid((unsigned)(512 * LPR / pbt), (unsigned)tb);  // 512 rows / rows per workgroup
+    if constexpr (LPR <= 64)
+        if (pbt == 64) {
+            hipLaunchKernelGGL((mf_pass_b<N1, 64, WRITE_Z>), grid, dim3(64), 0, ctx->stream, Y, r2s, ids, id0, thr2,
+                               twN1, bad, cand, counter, cap, spill_cap, zout);
+            return;
+        }
+    if constexpr (LPR <= 128)
+        if (pbt == 128) {
+            hipLaunchKernelGGL((mf_pass_b<N1, 128, WRITE_Z>), grid, dim3(128), 0, ctx->stream, Y, r2s, ids, id0, thr2,
+                               twN1, bad, cand, counter, cap, spill_cap, zout);
+            return;
+        }
+    hipLaunchKernelGGL((mf_pass_b<N1, 256, WRITE_Z>), grid, dim3(256), 0, ctx->stream, Y, r2s, ids, id0, thr2, twN1,
+                       bad, cand, counter, cap, spill_cap, zout);
+}
+
 template <bool WRITE_Z>
-static int launch_pass_b(hs_ctx *ctx, int N1, dim3 grid, const float2 *Y, const float *r2s, const int32_t *ids,
+static int launch_pass_b(hs_ctx *ctx, int N1, int tb, const float2 *Y, const float *r2s, const int32_t *ids,
                          int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
                          unsigned long long *counter, int64_t cap, int64_t spill_cap, float2 *zout) {
-#define HS_PB(NN)                                                                                         \
-    case NN:                                                                                              \
-        hipLaunchKernelGGL((mf_pass_b<NN, WRITE_Z>), grid, dim3(PB_THREADS), 0, ctx->stream, Y, r2s, ids, id0, thr2, \
-                           twN1, bad, cand, counter, cap, spill_cap, zout);                               \
+    const int pbt = pass_b_threads(ctx, N1);
+#define HS_PB(NN)                                                                                          \
+    case NN:                                                                                               \
+        launch_pass_b_n<NN, WRITE_Z>(ctx, pbt, tb, Y, r2s, ids, id0, thr2, twN1, bad, cand, counter, cap,   \
+                                     spill_cap, zout);                                                     \
         break;
     switch (N1) {
         HS_PB(16) HS_PB(32) HS_PB(64) HS_PB(128) HS_PB(256) HS_PB(512) HS_PB(1024) HS_PB(2048)
@@ -440,8 +471,7 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
             break;
         }
         HS_HIP(hipGetLastError());
-        const dim3 gb((unsigned)(512 * N1 / (16 * PB_THREADS)), (unsigned)tb);  // 512 rows / rows per block
-        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, gb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, sbuf,
+        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, tb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, sbuf,
                                       counter, stripe_cap, spill_cap, zout));
     }
     if (!WRITE_Z && cap > 0) {
@@ -451,8 +481,7 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     }
     unsigned long long hc[MF_STRIPES + 1];
     int32_t hbad = 0;
-    HS_TRY(read_back(ctx, counter, hc, sizeof(hc)));
-    HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
+    HS_TRY(read_back2(ctx, counter, hc, sizeof(hc), bad, &hbad, sizeof(hbad)));
     HS_REQUIRE(hbad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
                hbad);
     if (!WRITE_Z) {

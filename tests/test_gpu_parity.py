@@ -548,29 +548,40 @@ def test_background_fit_and_far_end_to_end_on_identical_triggers(ctx):
     assert np.allclose(far[fg], want, rtol=1e-12, atol=0)
 
 
-def test_matched_filter_does_not_depend_on_the_batch_budget(ctx):
-    """The autotuner's knob changes only the schedule: candidates are identical for any budget."""
+@pytest.mark.parametrize("n,fs", [(2 ** 13, 512.0), (2 ** 16, 2048.0), (2 ** 20, 2048.0)])
+def test_matched_filter_does_not_depend_on_the_schedule(ctx, n, fs):
+    """The autotuner's knobs (batch budget, pass-B tile) change only the schedule: candidates and
+    SNR series are identical for every setting (at 2^20 the 64-thread tile widens to one row)."""
     import torch
     from paper_2309_00019_amd import hs
-    _say("batch budget invariance")
-    n, fs, f_low = 2 ** 16, 2048.0, 20.0
+    _say(f"schedule invariance n={n}")
+    f_low = 20.0
     bank = _bank_for("tau", n, fs, f_low, count=37, seed=21)
     s = _strain(21, 0, n, fs, f_low, glitch_rate=0.1)
     psd_d = torch.as_tensor(analytic_psd(n, fs), device=ctx.device)
     pb = device_bank(ctx, bank, psd_d, f_low)
     spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
     ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
-    old = hs.hs_get_mf_batch_bytes(ctx)
-    out = []
+    old_b, old_t = hs.hs_get_mf_batch_bytes(ctx), hs.hs_get_mf_tile(ctx)
+    out, zs = [], []
     try:
-        for mb in (1, 3, 64):      # 2, 6 and all 37 templates per launch at n = 2^16
-            hs.hs_set_mf_batch_bytes(ctx, mb << 20)
-            assert hs.hs_get_mf_batch_bytes(ctx) == mb << 20
-            c = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 4.0), hs.CANDIDATE)
-            out.append(np.sort(c, order=["tpos", "m"]))
+        for tile in (64, 128, 256):
+            hs.hs_set_mf_tile(ctx, tile)
+            assert hs.hs_get_mf_tile(ctx) == tile
+            # one template per launch (at least 1 MiB), three, all 37
+            for nb in sorted({max(1 << 20, k * 8 * n) for k in (1, 3, 64)}):
+                hs.hs_set_mf_batch_bytes(ctx, nb)
+                assert hs.hs_get_mf_batch_bytes(ctx) == nb
+                c = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, 4.0), hs.CANDIDATE)
+                out.append(np.sort(c, order=["tpos", "m"]))
+            zs.append(hs.hs_snr_series(ctx, spec, n, fs, pb, ids[:3]).cpu().numpy())
     finally:
-        hs.hs_set_mf_batch_bytes(ctx, old)
-    assert len(out[0]) > 100
+        hs.hs_set_mf_batch_bytes(ctx, old_b)
+        hs.hs_set_mf_tile(ctx, old_t)
+    assert len(out[0]) > (100 if n >= 2 ** 16 else 10)
     assert all(np.array_equal(out[0], o) for o in out[1:])
+    assert all(np.array_equal(zs[0], z) for z in zs[1:])
     with pytest.raises(hs.HsError):
         hs.hs_set_mf_batch_bytes(ctx, 1000)
+    with pytest.raises(hs.HsError):
+        hs.hs_set_mf_tile(ctx, 96)
