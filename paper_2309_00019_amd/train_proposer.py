@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--data", default=None, help="save the collected samples here (npz); with --reuse, load them")
     ap.add_argument("--reuse", action="store_true")
+    ap.add_argument("--train-seed0", type=int, default=10000,
+                    help="first training realisation seed (the early-stopping and held-out sets use 40000.. and "
+                         "20000..; keep the training range clear of them)")
     args = ap.parse_args()
     # host workers are spawned (fresh interpreters that never load the GPU runtime)
     import synth
@@ -113,8 +116,12 @@ def main():
         xt, yt, it, nt, xs, ys, is_, ns, xv, yv, iv, nv = (z[k] for k in keys)
         nt, ns, nv = int(nt), int(ns), int(nv)
     else:
-        # disjoint seed ranges: training 10000.., early stopping 40000.., held-out 20000..
-        r_train = [10000 + r for r in range(-(-args.train // ps))]
+        # disjoint seed ranges: training train_seed0.., early stopping 40000.., held-out 20000..
+        r_train = [args.train_seed0 + r for r in range(-(-args.train // ps))]
+        lo, hi = r_train[0], r_train[-1]
+        for a, b in ((40000, 40000 + -(-args.stop // ps)), (20000, 20000 + -(-args.val // ps))):
+            if lo < b and a <= hi:
+                raise SystemExit(f"training realisations {lo}..{hi} overlap the range {a}..{b - 1}")
         r_stop = [40000 + r for r in range(-(-args.stop // ps))]
         r_val = [20000 + r for r in range(-(-args.val // ps))]
         xt, yt, it, nt = collect(ctx, pool, r_train, ps, coarse_h, coarse_l, psd_h, psd_l, cfg, "train")
@@ -142,7 +149,7 @@ def main():
                 best_epoch=best_epoch, n_stop=len(ys),
                 lr=args.lr, lr_final=args.lr_final, val_hit=hit, val_loss=proposer.mean_loss(ctx, model, xv, yv), val_mean_cells=cells, val_plain_hit=plain_hit,
                 loss_first=hist[0], loss_last=hist[-1], train_seconds=t_train,
-                seeds="realisations: training 10000.., early stopping 40000.., held-out 20000.. (cfg 2)",
+                seeds=f"realisations: training {args.train_seed0}.., early stopping 40000.., held-out 20000.. (cfg 2)",
                 p_table=json.dumps([list(map(float, r)) for r in table]))
     prop = proposer.Proposer(model, p_cum, proposer.Q_EDGES, cfg.mc_frac, meta, args.rho_low, args.p_low)
     prop.save(args.out or proposer.DEFAULT_PATH)
