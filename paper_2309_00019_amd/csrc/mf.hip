@@ -19,6 +19,12 @@
 // through LDS, and a second radix-16 DFT finishes each 256-point transform.
 // Pass B: each lane holds 16 points of a row; N1/16 lanes share a row; radix-16 passes with
 // LDS exchanges (Stockham indexing), the last pass ending in registers for the epilogue.
+// Both passes are bound by latency more than by bandwidth (a few workgroups per CU, LDS-limited),
+// so every global load of a workgroup is issued before its first LDS barrier: the band loads,
+// one per-call record with the template's band and scale (instead of a chain ids -> offset ->
+// band), and in pass B one twiddle per radix group, whose powers are then formed by at most 14
+// products (relative error ~1e-6, far below the SNR tolerance) instead of table loads that would
+// wait behind each barrier.
 #include <cmath>
 
 #include "dft.h"
@@ -59,36 +65,53 @@ __device__ __forceinline__ void mf_store_one(hs_candidate *lists, unsigned long 
     }
 }
 
-__global__ void mf_validate(const int32_t *__restrict__ ids, int32_t n_ids, int32_t n_tmpl,
-                            const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
-                            const int32_t *__restrict__ khi, int64_t half, int32_t *__restrict__ bad) {
+// Per-call work list: one record per position of tmpl_ids, so each workgroup of pass A / pass B
+// finds its template's band and scale with a single scalar load.  An id outside the bank or a
+// band outside [1, n/2 - 1] sets *bad and gets an empty band and a zero scale (the passes then
+// read nothing from the bank; the call reports the error).
+struct alignas(32) MfItem {
+    int64_t base;  // element index of bin 0 in the spectra (offset - k0)
+    int32_t lo, hi;
+    float sc;      // rho^2 scale of the template's storage
+    int32_t pad[3];
+};
+
+__global__ void mf_items(const int32_t *__restrict__ ids, int32_t n_ids, int32_t n_tmpl,
+                         const int64_t *__restrict__ offset, const int32_t *__restrict__ k0,
+                         const int32_t *__restrict__ klo, const int32_t *__restrict__ khi,
+                         const float *__restrict__ r2scale, int64_t half, MfItem *__restrict__ items,
+                         int32_t *__restrict__ bad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_ids) return;
+    MfItem it{0, 1, 0, 0.0f, {0, 0, 0}};
     const int32_t t = ids[i];
     if (t < 0 || t >= n_tmpl) {
         atomicOr(bad, 1);
-        return;
+    } else if (klo[t] < 1 || klo[t] < k0[t] || khi[t] > half - 1) {
+        atomicOr(bad, 2);
+    } else {
+        it.base = offset[t] - k0[t];
+        it.lo = klo[t];
+        it.hi = khi[t];
+        it.sc = r2scale[t];
     }
-    if (klo[t] < 1 || klo[t] < k0[t] || khi[t] > half - 1) atomicOr(bad, 2);
+    items[i] = it;
 }
 
 // 256 threads, at least 4 waves per SIMD (caps VGPRs at 128 so 4 workgroups fit a CU).
 template <typename ST>
 __global__ __launch_bounds__(256, 4) void mf_pass_a(
     const float2 *__restrict__ dspec, const typename ST::elem *__restrict__ spectra,
-    const int64_t *__restrict__ offset, const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
-    const int32_t *__restrict__ khi, const int32_t *__restrict__ ids, int32_t id0, int32_t N1,
-    const float2 *__restrict__ tw512, const float2 *__restrict__ twlo, const float2 *__restrict__ twhi,
-    const int32_t *__restrict__ bad, float2 *__restrict__ Y) {
+    const MfItem *__restrict__ items, int32_t id0, int32_t N1, const float2 *__restrict__ tw512,
+    const float2 *__restrict__ twlo, const float2 *__restrict__ twhi, float2 *__restrict__ Y) {
     __shared__ float2 lds[16 * PA_LDS_LSTRIDE];
-    if (*bad) return;
     const int tb = blockIdx.y;
-    const int t = ids[id0 + tb];
+    const MfItem it = items[id0 + tb];
     const int c = threadIdx.x & 15;
     const int l = threadIdx.x >> 4;
     const int k1 = blockIdx.x * 16 + c;
-    const int64_t base = offset[t] - k0[t];
-    const int lo = klo[t], hi = khi[t];
+    const int64_t base = it.base;
+    const int lo = it.lo, hi = it.hi;
 
     // All 32 band loads are issued before any product uses them: a use right after each
     // band-tested load would make the wavefront wait for every row in turn.
@@ -210,28 +233,40 @@ __device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int
     for (int e = 0; e < 16; ++e) row[lds_map<N1>(pass_out_index<LPR, R, Ns>(ln, e))] = v[e];
 }
 
+// Reads the inputs of a radix-R pass at sub-transform size Ns from LDS: butterfly j = ln + LPR b
+// takes row[j + r N1/R], multiplied by W_N1^{k r S} (S = N1 / (Ns R), k = j mod Ns), and runs the
+// radix-R DFT.  The twiddles are the powers of one preloaded base per b, base[b] = W_N1^{k S},
+// formed by at most R - 2 products: no table load waits behind the LDS barrier.
 template <int N1, int LPR, int R, int Ns>
-__device__ __forceinline__ void lds_read_pass(float2 *v, const float2 *row, int ln, const float2 *tw) {
+__device__ __forceinline__ void lds_read_pass_pow(float2 *v, const float2 *row, int ln, const float2 *base) {
 #pragma unroll
     for (int b = 0; b < 16 / R; ++b) {
         const int j = ln + LPR * b;
-        const int k = j % Ns;
+        float2 w = base[b];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float2 x = row[lds_map<N1>(j + r * (N1 / R))];
-            if (r > 0) x = cmul(x, tw[k * r * (N1 / (Ns * R))]);
+            if (r == 1) x = cmul(x, w);
+            if (r > 1) {
+                w = cmul(w, base[b]);
+                x = cmul(x, w);
+            }
             v[b * R + r] = x;
         }
         dft<R, 1>(v + b * R);
     }
 }
 
-// PBT threads per workgroup (64, 128 or 256; at least one row of N1/16 lanes): the pass-B tile,
-// PBT / (N1/16) rows per workgroup.  The tile is chosen per context (hs_set_mf_tile).
+// Table entries W_N1^{k S}, k = (ln + LPR b) mod Ns, S = N1 / (Ns R), for every b of a pass.
+template <int N1, int LPR, int R, int Ns>
+__device__ __forceinline__ void pass_bases(float2 *base, int ln, const float2 *tw) {
+#pragma unroll
+    for (int b = 0; b < 16 / R; ++b) base[b] = tw[((ln + LPR * b) % Ns) * (N1 / (Ns * R))];
+}
+
 template <int N1, int PBT, bool WRITE_Z>
-__global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, const float *__restrict__ r2scale,
-                                                 const int32_t *__restrict__ ids, int32_t id0, float thr2,
-                                                 const float2 *__restrict__ twN1, const int32_t *__restrict__ bad,
+__global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, const MfItem *__restrict__ items,
+                                                 int32_t id0, float thr2, const float2 *__restrict__ twN1,
                                                  hs_candidate *__restrict__ cand,
                                                  unsigned long long *__restrict__ counter, int64_t cap,
                                                  int64_t spill_cap, float2 *__restrict__ zout) {
@@ -244,7 +279,6 @@ __global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, c
     __shared__ float2 lds[LDS_N];
     __shared__ unsigned int s_count;
     __shared__ unsigned long long s_base, s_spill;
-    if (*bad) return;
     if (threadIdx.x == 0) s_count = 0;
     const int tb = blockIdx.y;
     const int lr = threadIdx.x / LPR;
@@ -252,27 +286,29 @@ __global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, c
     const int m2 = blockIdx.x * RPB + lr;
     const float2 *src = Y + ((size_t)tb * 512 + m2) * (size_t)N1;
 
+    const float sc = items[id0 + tb].sc;
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = src[ln + r * LPR];
+    float2 base2[R2 > 1 ? 16 / R2 : 1], base3[R3 > 1 ? 16 / R3 : 1];
+    if constexpr (R2 > 1) pass_bases<N1, LPR, R2, 16>(base2, ln, twN1);
+    if constexpr (R3 > 1) pass_bases<N1, LPR, R3, 16 * R2>(base3, ln, twN1);
     dft16<1>(v);
     float2 *row = lds + (N1 > 16 ? lr * ROW : 0);
     if constexpr (R2 > 1) {
         lds_write_pass<N1, LPR, 16, 1>(row, v, ln);
         __syncthreads();
-        lds_read_pass<N1, LPR, R2, 16>(v, row, ln, twN1);
+        lds_read_pass_pow<N1, LPR, R2, 16>(v, row, ln, base2);
     }
     if constexpr (R3 > 1) {
         __syncthreads();
         lds_write_pass<N1, LPR, R2, 16>(row, v, ln);
         __syncthreads();
-        lds_read_pass<N1, LPR, R3, 16 * R2>(v, row, ln, twN1);
+        lds_read_pass_pow<N1, LPR, R3, 16 * R2>(v, row, ln, base3);
     }
     constexpr int RL = R3 > 1 ? R3 : (R2 > 1 ? R2 : 16);
     constexpr int NsL = R3 > 1 ? 16 * R2 : (R2 > 1 ? 16 : 1);
 
-    const int t = ids[id0 + tb];
-    const float sc = r2scale[t];
     if constexpr (WRITE_Z) {
         const float zs = sqrtf(sc);
         float2 *zt = zout + (size_t)(id0 + tb) * 512 * (size_t)N1;
@@ -354,36 +390,36 @@ static int pass_b_threads(const hs_ctx *ctx, int N1) {
 }
 
 template <int N1, bool WRITE_Z>
-static void launch_pass_b_n(hs_ctx *ctx, int pbt, int tb, const float2 *Y, const float *r2s, const int32_t *ids,
-                            int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
-                            unsigned long long *counter, int64_t cap, int64_t spill_cap, float2 *zout) {
+static void launch_pass_b_n(hs_ctx *ctx, int pbt, int tb, const float2 *Y, const MfItem *items, int32_t id0,
+                            float thr2, const float2 *twN1, hs_candidate *cand, unsigned long long *counter,
+                            int64_t cap, int64_t spill_cap, float2 *zout) {
     constexpr int LPR = N1 / 16;
     const dim3 grid((unsigned)(512 * LPR / pbt), (unsigned)tb);  // 512 rows / rows per workgroup
     if constexpr (LPR <= 64)
         if (pbt == 64) {
-            hipLaunchKernelGGL((mf_pass_b<N1, 64, WRITE_Z>), grid, dim3(64), 0, ctx->stream, Y, r2s, ids, id0, thr2,
-                               twN1, bad, cand, counter, cap, spill_cap, zout);
+            hipLaunchKernelGGL((mf_pass_b<N1, 64, WRITE_Z>), grid, dim3(64), 0, ctx->stream, Y, items, id0, thr2,
+                               twN1, cand, counter, cap, spill_cap, zout);
             return;
         }
     if constexpr (LPR <= 128)
         if (pbt == 128) {
-            hipLaunchKernelGGL((mf_pass_b<N1, 128, WRITE_Z>), grid, dim3(128), 0, ctx->stream, Y, r2s, ids, id0, thr2,
-                               twN1, bad, cand, counter, cap, spill_cap, zout);
+            hipLaunchKernelGGL((mf_pass_b<N1, 128, WRITE_Z>), grid, dim3(128), 0, ctx->stream, Y, items, id0, thr2,
+                               twN1, cand, counter, cap, spill_cap, zout);
             return;
         }
-    hipLaunchKernelGGL((mf_pass_b<N1, 256, WRITE_Z>), grid, dim3(256), 0, ctx->stream, Y, r2s, ids, id0, thr2, twN1,
-                       bad, cand, counter, cap, spill_cap, zout);
+    hipLaunchKernelGGL((mf_pass_b<N1, 256, WRITE_Z>), grid, dim3(256), 0, ctx->stream, Y, items, id0, thr2, twN1,
+                       cand, counter, cap, spill_cap, zout);
 }
 
 template <bool WRITE_Z>
-static int launch_pass_b(hs_ctx *ctx, int N1, int tb, const float2 *Y, const float *r2s, const int32_t *ids,
-                         int32_t id0, float thr2, const float2 *twN1, const int32_t *bad, hs_candidate *cand,
-                         unsigned long long *counter, int64_t cap, int64_t spill_cap, float2 *zout) {
+static int launch_pass_b(hs_ctx *ctx, int N1, int tb, const float2 *Y, const MfItem *items, int32_t id0, float thr2,
+                         const float2 *twN1, hs_candidate *cand, unsigned long long *counter, int64_t cap,
+                         int64_t spill_cap, float2 *zout) {
     const int pbt = pass_b_threads(ctx, N1);
 #define HS_PB(NN)                                                                                          \
     case NN:                                                                                               \
-        launch_pass_b_n<NN, WRITE_Z>(ctx, pbt, tb, Y, r2s, ids, id0, thr2, twN1, bad, cand, counter, cap,   \
-                                     spill_cap, zout);                                                     \
+        launch_pass_b_n<NN, WRITE_Z>(ctx, pbt, tb, Y, items, id0, thr2, twN1, cand, counter, cap, spill_cap, \
+                                     zout);                                                                \
         break;
     switch (N1) {
         HS_PB(16) HS_PB(32) HS_PB(64) HS_PB(128) HS_PB(256) HS_PB(512) HS_PB(1024) HS_PB(2048)
@@ -436,16 +472,19 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     unsigned long long *counter;
     hs_candidate *sbuf;
     int32_t *bad;
+    MfItem *items;
     Carver cv;
     cv.add(&Y, (size_t)tb_max * n);
     cv.add(&counter, MF_STRIPES + 1);
     cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap + spill_cap + 1);
     cv.add(&bad, 1);
+    cv.add(&items, (size_t)n_ids);
     HS_TRY(cv.commit(ctx));
     HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), MF_STRIPES + 1, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
-    hipLaunchKernelGGL(mf_validate, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
-                       bank->n_tmpl, bank->k0, bank->k_lo, bank->k_hi, n / 2, bad);
+    hipLaunchKernelGGL(mf_items, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
+                       bank->n_tmpl, bank->offset, bank->k0, bank->k_lo, bank->k_hi, bank->rho2_scale, n / 2, items,
+                       bad);
     HS_HIP(hipGetLastError());
 
     const float thr2 = thr * thr;
@@ -456,23 +495,23 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
         switch (bank->dtype) {
         case HS_F32:
             hipLaunchKernelGGL(mf_pass_a<StoreF32>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const float2 *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+                               static_cast<const float2 *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
+                               twhi, Y);
             break;
         case HS_BF16:
             hipLaunchKernelGGL(mf_pass_a<StoreBF16>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+                               static_cast<const uint32_t *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
+                               twhi, Y);
             break;
         default:
             hipLaunchKernelGGL(mf_pass_a<StoreF16>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const uint32_t *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                               bank->k_hi, ids, (int32_t)id0, N1, tw512, twlo, twhi, bad, Y);
+                               static_cast<const uint32_t *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
+                               twhi, Y);
             break;
         }
         HS_HIP(hipGetLastError());
-        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, tb, Y, bank->rho2_scale, ids, (int32_t)id0, thr2, twN1, bad, sbuf,
-                                      counter, stripe_cap, spill_cap, zout));
+        HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, tb, Y, items, (int32_t)id0, thr2, twN1, sbuf, counter, stripe_cap,
+                                      spill_cap, zout));
     }
     if (!WRITE_Z && cap > 0) {
         hipLaunchKernelGGL(mf_compact, dim3(16, MF_STRIPES + 1), dim3(256), 0, ctx->stream, sbuf, counter,
