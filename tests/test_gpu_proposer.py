@@ -217,32 +217,36 @@ def test_followup_cells_exact(ctx, seed, n_seg):
         assert torch.equal(ids_a[s, :counts_a[s]], ids_p[s, :counts_p[s]])
 
 
-@pytest.mark.parametrize("use_proposer", [False, True])
-def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer):
+@pytest.mark.parametrize("use_proposer,n_seg", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer, n_seg):
     """The whole two-stage search (whitening, stage 1 with chi-square, coincidence over the stage-1
     slides, plain or proposer follow-up, stage 2, coincidence over the background slides) against
-    the oracle's pipeline on a short segment pair with a loud injection."""
+    the oracle's pipeline on short segments with a loud injection (in the last segment); with two
+    segments per detector the ticks, the per-segment follow-up lists and the slide ring span both."""
     import torch
     from paper_2309_00019_amd import hs, search, workload
     from paper_2309_00019_amd.proposer import Proposer
     from helpers import analytic_psd
-    _say(f"end to end proposer={use_proposer}")
+    _say(f"end to end proposer={use_proposer} segments={n_seg}")
     n, fs, f_low = 2 ** 15, 2048.0, 20.0
     g = synth.rng(78, 0, 0, synth.BANK)
     m1, m2 = synth.bank_by_tau0(60, 4.0, 10.0, 1.0, 2.0, g)
     fine = synth.taylorf2_bank(m1, m2, n, fs, f_low)
     coarse = synth.taylorf2_bank(m1[::6], m2[::6], n // 4, fs / 4, f_low)
     t = 24
-    sh, _ = synth.make_strain(78, 0, 0, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)])
-    sl, _ = synth.make_strain(78, 1, 0, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)])
+    last = n_seg - 1
+    sh = [synth.make_strain(78, 0, s, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)]
+                            if s == last else [])[0] for s in range(n_seg)]
+    sl = [synth.make_strain(78, 1, s, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)]
+                            if s == last else [])[0] for s in range(n_seg)]
     psd = analytic_psd(n, fs)
     d = ctx.device
     psd_d = torch.as_tensor(psd, device=d)
     n1 = n // 4
     fine_h, = workload.make_banks(ctx, n, fs, f_low, m1, m2, [psd_d])
     coarse_h, = workload.make_banks(ctx, n1, fs / 4, f_low, m1[::6], m2[::6], [psd_d[: n1 // 2 + 1].contiguous()])
-    spec_h = hs.hs_whiten(ctx, torch.as_tensor(sh, device=d), fs, f_low, psd_d)[None]
-    spec_l = hs.hs_whiten(ctx, torch.as_tensor(sl, device=d), fs, f_low, psd_d)[None]
+    spec_h = torch.stack([hs.hs_whiten(ctx, torch.as_tensor(x, device=d), fs, f_low, psd_d) for x in sh])
+    spec_l = torch.stack([hs.hs_whiten(ctx, torch.as_tensor(x, device=d), fs, f_low, psd_d) for x in sl])
     cfg = search.SearchConfig(fs=fs, f_low=f_low, n_sh1=2, t_sh1_sec=3.0, n_slides=10, step_sec=0.1, rho1=6.0,
                               chisq_rho_min=5.0, edges=(8.0,))
     kw = dict(n_sh1=2, t_sh1_sec=3.0, n_slides=10, step_sec=0.1, rho1=6.0, chisq_rho_min=5.0, edges=(8.0,))
@@ -252,7 +256,8 @@ def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer):
         prop = Proposer(torch.as_tensor(m, device=d), 0.9, (1.75, 2.5, 3.25), 0.05, {}, 5.75, 0.5)
         oprop = (m.astype(np.float64), (1.75, 2.5, 3.25), 0.9, 5.75, 0.5)
     res = search.hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_h, fine_h, fine_h, cfg, proposer=prop)
-    ref = oracle.hierarchical_search([sh], [sl], [psd], [psd], fs, f_low, coarse, fine, proposer=oprop, **kw)
+    ref = oracle.hierarchical_search(sh, sl, [psd] * n_seg, [psd] * n_seg, fs, f_low, coarse, fine, proposer=oprop,
+                                     **kw)
     # stage-1 coincidences well above the follow-up threshold agree exactly
     c1 = hs.as_records(res.stage1_coincs, hs.COINC)
     r1 = ref["coinc1"]["coincs"]
@@ -262,8 +267,9 @@ def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer):
     got1 = key(c1, c1["snr_c"] >= lo)
     want1 = key(r1, np.asarray(r1["snr_c"]) >= lo)
     assert got1 == want1 and len(want1) > 0
-    # the followed fine templates
-    assert np.array_equal(res.fine_ids[0].cpu().numpy(), ref["fine_ids"][0])
+    # the followed fine templates of every segment
+    for s in range(n_seg):
+        assert np.array_equal(res.fine_ids[s].cpu().numpy(), ref["fine_ids"][s]), s
     # the injection: the loudest zero-lag stage-2 coincidence, same template and ticks
     c2 = hs.as_records(res.coincs, hs.COINC)
     r2 = ref["coinc"]["coincs"]
@@ -281,4 +287,4 @@ def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer):
         (int(r2["tmpl"][ir]), int(r2["tick_h"][ir]), int(r2["tick_l"][ir]))
     assert abs(float(zg["snr_c"][ig]) / float(r2["snr_c"][ir]) - 1.0) < 1e-3
     if not use_proposer:
-        assert abs(int(zg["tick_h"][ig]) - 7.0 * 51200) <= 0.1 * 51200 and zg["snr_c"][ig] >= 8.0
+        assert abs(int(zg["tick_h"][ig]) - (last * n * 25 + 7.0 * 51200)) <= 0.1 * 51200 and zg["snr_c"][ig] >= 8.0
