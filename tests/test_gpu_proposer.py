@@ -288,3 +288,51 @@ def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer, n_seg)
     assert abs(float(zg["snr_c"][ig]) / float(r2["snr_c"][ir]) - 1.0) < 1e-3
     if not use_proposer:
         assert abs(int(zg["tick_h"][ig]) - (last * n * 25 + 7.0 * 51200)) <= 0.1 * 51200 and zg["snr_c"][ig] >= 8.0
+
+
+@pytest.mark.parametrize("n_seg", [1, 2])
+def test_flat_search_matches_oracle_end_to_end(ctx, n_seg):
+    """The flat search (every fine template on every segment, chi-square re-weighting, 20-slide
+    coincidence with background counts) against the oracle's flat pipeline on glitchy segments
+    with an injection in the last one."""
+    import torch
+    from paper_2309_00019_amd import hs, search, workload
+    from helpers import analytic_psd
+    _say(f"flat end to end segments={n_seg}")
+    n, fs, f_low = 2 ** 15, 2048.0, 20.0
+    g = synth.rng(79, 0, 0, synth.BANK)
+    m1, m2 = synth.bank_by_tau0(40, 4.0, 10.0, 1.0, 3.0, g)
+    fine = synth.taylorf2_bank(m1, m2, n, fs, f_low)
+    t, last = 17, n_seg - 1
+    inj = lambda s, tc, ph: [dict(m1=m1[t], m2=m2[t], t_c=tc, phi_c=ph, snr=11.0)] if s == last else []
+    sh = [synth.make_strain(79, 0, s, n, fs, f_low, glitch_rate=0.3, injections=inj(s, 5.0, 0.3))[0]
+          for s in range(n_seg)]
+    sl = [synth.make_strain(79, 1, s, n, fs, f_low, glitch_rate=0.3, injections=inj(s, 5.004, 1.3))[0]
+          for s in range(n_seg)]
+    psd = analytic_psd(n, fs)
+    d = ctx.device
+    psd_d = torch.as_tensor(psd, device=d)
+    fine_h, = workload.make_banks(ctx, n, fs, f_low, m1, m2, [psd_d])
+    spec_h = torch.stack([hs.hs_whiten(ctx, torch.as_tensor(x, device=d), fs, f_low, psd_d) for x in sh])
+    spec_l = torch.stack([hs.hs_whiten(ctx, torch.as_tensor(x, device=d), fs, f_low, psd_d) for x in sl])
+    edges = (6.0, 7.0, 8.0)
+    cfg = search.SearchConfig(fs=fs, f_low=f_low, n_slides=20, step_sec=0.1, chisq_rho_min=5.0, edges=edges)
+    res = search.flat_search(ctx, spec_h, spec_l, fine_h, fine_h, cfg)
+    ref = oracle.flat_search(sh, sl, [psd] * n_seg, [psd] * n_seg, fs, f_low, fine, n_slides=20, step_sec=0.1,
+                             edges=edges, chisq_rho_min=5.0)
+    c2 = hs.as_records(res.coincs, hs.COINC)
+    r2 = ref["coinc"]["coincs"]
+    key = lambda c, sel: sorted(zip(np.asarray(c["slide"])[sel], np.asarray(c["tmpl"])[sel],
+                                    np.asarray(c["tick_h"])[sel], np.asarray(c["tick_l"])[sel]))
+    hi = 6.0
+    want = key(r2, np.asarray(r2["snr_c"]) >= hi)
+    assert key(c2, c2["snr_c"] >= hi) == want and len(want) > 0
+    # background counts: equal, up to the coincidences whose statistic sits within the SNR
+    # tolerance of an edge (they may fall on either side)
+    rs = np.asarray(r2["snr_c"], np.float64)[np.asarray(r2["slide"]) >= 1]
+    for e, (gb, rb) in enumerate(zip(res.bg_counts, ref["coinc"]["bg_counts"])):
+        near = int(np.sum(np.abs(rs / edges[e] - 1.0) <= 2e-4))
+        assert abs(int(gb) - int(rb)) <= near, (edges[e], gb, rb, near)
+    zg = c2[c2["slide"] == 0]
+    ig = int(np.argmax(zg["snr_c"]))
+    assert abs(int(zg["tick_h"][ig]) - (last * n * 25 + 5.0 * 51200)) <= 0.1 * 51200 and zg["snr_c"][ig] >= 8.0
