@@ -31,12 +31,6 @@ struct RawCoinc {
     float stat;
 };
 
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {  // b > 0
-    int64_t q = a / b;
-    if ((a % b != 0) && (a < 0)) --q;
-    return q;
-}
-__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
 __device__ __forceinline__ int64_t pos_mod(int64_t a, int64_t T) {
     int64_t r = a % T;
     return r < 0 ? r + T : r;
@@ -44,14 +38,24 @@ __device__ __forceinline__ int64_t pos_mod(int64_t a, int64_t T) {
 
 struct SlideGeom {
     int64_t K, step, window, wrap, jmax;
+    double inv_step;  // 1 / step, rounded
 };
+
+// floor(a / b) for b > 0 and |a| < 2^50: a float64 estimate (within one of the quotient) corrected
+// to the exact integer; int64 division is a long instruction sequence on the GPU.
+__device__ __forceinline__ int64_t floor_div_r(int64_t a, int64_t b, double inv_b) {
+    int64_t q = (int64_t)floor((double)a * inv_b);
+    if (q * b > a) --q;
+    else if ((q + 1) * b <= a) ++q;
+    return q;
+}
 
 // Calls f(k) for every slide k in [0, K] with |circ(d - k step)| <= window, d in [0, T).
 template <typename F>
 __device__ __forceinline__ void for_each_slide(int64_t d, const SlideGeom &g, F f) {
     for (int64_t jw = -1; jw <= g.jmax; ++jw) {
-        int64_t lo = ceil_div(d - g.window + jw * g.wrap, g.step);
-        int64_t hi = floor_div(d + g.window + jw * g.wrap, g.step);
+        int64_t lo = -floor_div_r(g.window - d - jw * g.wrap, g.step, g.inv_step);  // ceil
+        int64_t hi = floor_div_r(d + g.window + jw * g.wrap, g.step, g.inv_step);
         if (lo < 0) lo = 0;
         if (hi > g.K) hi = g.K;
         for (int64_t k = lo; k <= hi; ++k) f(k);
@@ -97,7 +101,8 @@ __global__ void co_pair_count(const hs_trigger *__restrict__ h, int64_t nh, cons
     } else {
         for (uint64_t p = lstart[a.tmpl]; p < lstart[a.tmpl + 1]; ++p) {
             const hs_trigger b = l[lidx[p]];
-            const int64_t d = pos_mod(a.tick - b.tick, g.wrap);
+            int64_t d = a.tick - b.tick;  // both ticks in [0, wrap)
+            if (d < 0) d += g.wrap;
             for_each_slide(d, g, [&](int64_t) { ++c; });
         }
     }
@@ -117,7 +122,8 @@ __global__ void co_pair_write(const hs_trigger *__restrict__ h, int64_t nh, cons
     for (uint64_t p = lstart[a.tmpl]; p < lstart[a.tmpl + 1]; ++p) {
         const uint32_t jl = lidx[p];
         const hs_trigger b = l[jl];
-        const int64_t d = pos_mod(a.tick - b.tick, g.wrap);
+        int64_t d = a.tick - b.tick;  // both ticks in [0, wrap)
+        if (d < 0) d += g.wrap;
         const float stat = (float)(sa + (double)b.snr * (double)b.snr);
         for_each_slide(d, g, [&](int64_t k) {
             raw[w++] = RawCoinc{(uint32_t)i, jl, (uint32_t)k, stat};
@@ -354,7 +360,9 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     const int64_t bins = (n_slides + 1) * n_tiles;
     HS_REQUIRE(bins <= (int64_t(1) << 28), "hs_timeslide_coinc: %lld (slide, tile) bins exceed 2^28",
                (long long)bins);
-    SlideGeom g{n_slides, step, window, wrap, (n_slides * step + window) / wrap + 1};
+    HS_REQUIRE(n_slides <= (int64_t(1) << 50) / step && n_slides * step + 3 * wrap < (int64_t(1) << 50),
+               "hs_timeslide_coinc: n_slides * step + 3 wrap must stay below 2^50 ticks");
+    SlideGeom g{n_slides, step, window, wrap, (n_slides * step + window) / wrap + 1, 1.0 / (double)step};
     BinGeom bgm{cluster_w, n_tiles};
 
     // --- phase 1: group L by template, count pairs per H trigger -------------------------------
