@@ -245,7 +245,8 @@ int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank 
  *   edges host float [n_edges]; bg_counts host int64 [n_edges]
  *   out device hs_coinc [cap]; n_out host
  * Requires 0 <= 2 window < wrap, step > 0, 0 < cluster_w < 65536,
- * n_slides >= 0, 0 <= n_edges <= 4096 and no NaN edge (HS_EINVAL otherwise).
+ * n_slides >= 0, n_slides * step + 3 wrap < 2^50, 0 <= n_edges <= 4096 and no
+ * NaN edge (HS_EINVAL otherwise).
  * Background time is n_slides * wrap ticks (Eq. (6) T_b).
  */
 int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, const hs_trigger *l,
