@@ -29,7 +29,7 @@ __global__ void clu_bin(const hs_candidate *__restrict__ cand, int64_t n_cand, i
         atomicOr(bad, 1);
         return;
     }
-    const int64_t b = (int64_t)c.tpos * n_tiles + c.m / W;
+    const int64_t b = (int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W;
     atomicAdd(&cnt[b], 1u);
     atomicMax(&best[b], (unsigned long long)cand_key(c.rho2, c.m));
 }
@@ -41,7 +41,7 @@ __global__ void clu_scatter(const hs_candidate *__restrict__ cand, int64_t n_can
     if (i >= n_cand) return;
     const hs_candidate c = cand[i];
     if (c.tpos < 0 || c.tpos >= n_ids || c.m < 0 || (int64_t)c.m >= n) return;
-    const int64_t b = (int64_t)c.tpos * n_tiles + c.m / W;
+    const int64_t b = (int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W;
     const uint32_t p = atomicAdd(&cursor[b], 1u);
     lists[start[b] + p] = (uint32_t)i;
 }
@@ -54,7 +54,7 @@ __global__ void clu_champion(const hs_candidate *__restrict__ cand, int64_t n_ca
     if (i >= n_cand) return;
     const hs_candidate c = cand[i];
     if (c.tpos < 0 || c.tpos >= n_ids || c.m < 0 || (int64_t)c.m >= n) return;
-    const int64_t tile = c.m / W;
+    const int64_t tile = (uint32_t)c.m / (uint32_t)W;
     const int64_t b = (int64_t)c.tpos * n_tiles + tile;
     const uint64_t key = cand_key(c.rho2, c.m);
     if (key != best[b]) return;
@@ -107,6 +107,9 @@ extern "C" int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_
     if (n_cand == 0 || n_ids == 0) return HS_OK;
     HS_REQUIRE(cand && tmpl_ids && (out || cap == 0), "hs_cluster_triggers: null argument");
     HS_HIP(hipSetDevice(ctx->device));
+    // a window of n or more samples joins every candidate of a template (one tile): the same
+    // clustering as a window of n, which keeps the tile index a 32-bit quotient in the kernels
+    if (window > n) window = n;
     const int64_t n_tiles = cdiv(n, window);
     const int64_t bins = (int64_t)n_ids * n_tiles;
     HS_REQUIRE(bins <= (int64_t(1) << 28), "hs_cluster_triggers: %lld (template, tile) bins exceed 2^28; "
