@@ -138,10 +138,11 @@ __device__ __forceinline__ uint64_t coinc_key(float stat, int32_t tmpl, int64_t 
 
 struct BinGeom {
     int64_t cw, n_tiles;
+    double inv_cw;  // 1 / cw, rounded
 };
 
 __device__ __forceinline__ int64_t coinc_bin(const RawCoinc &r, int64_t tick_h, const BinGeom &bg, int64_t *tile) {
-    *tile = tick_h / bg.cw;
+    *tile = floor_div_r(tick_h, bg.cw, bg.inv_cw);
     return (int64_t)r.k * bg.n_tiles + *tile;
 }
 
@@ -363,7 +364,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     HS_REQUIRE(n_slides <= (int64_t(1) << 50) / step && n_slides * step + 3 * wrap < (int64_t(1) << 50),
                "hs_timeslide_coinc: n_slides * step + 3 wrap must stay below 2^50 ticks");
     SlideGeom g{n_slides, step, window, wrap, (n_slides * step + window) / wrap + 1, 1.0 / (double)step};
-    BinGeom bgm{cluster_w, n_tiles};
+    BinGeom bgm{cluster_w, n_tiles, 1.0 / (double)cluster_w};
 
     // --- phase 1: group L by template, count pairs per H trigger -------------------------------
     uint32_t *lcnt, *lcur, *lidx, *pc;
