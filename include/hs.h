@@ -105,7 +105,8 @@ int hs_abi_version(void);
 
 /* Matched-filter schedule: bytes of the pass-A -> pass-B intermediate per batch
  * (batch = bytes / (8 n) templates, at least 1).  Default 128 MiB, or the
- * HS_MF_BATCH_MB environment variable at hs_create; set by the autotuner.
+ * HS_MF_BATCH_MB environment variable at hs_create (MiB, used only when in
+ * [1, 65536]); set by the autotuner.
  * HS_EINVAL if bytes < 1 MiB or > 64 GiB.  hs_get_mf_batch_bytes returns the
  * current value (0 for a NULL context). */
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes);
@@ -137,7 +138,8 @@ int hs_welch_psd(hs_ctx *ctx, const float *strain, int64_t n, double fs, int64_t
  * zero for k < k_lo; k_lo = max(1, ceil(f_low n / fs)) (lower limit of Eq. (2)).
  * The transform runs in float32; the division in float64.
  *   strain   device float  [n]          n a power of two, 2^10 <= n <= 2^22
- *   psd      device double [n/2 + 1]    positive on the band
+ *   psd      device double [n/2 + 1]    positive and finite on the band (not
+ *            checked here: the call does not synchronise; hs_prepare_bank checks it)
  *   spec_out device complex64 [n/2]     bins 0..n/2-1
  * The leading m/2 bins of spec_out are also the whitened spectrum of the same
  * data ideally decimated to m samples (same df), which is how a lower-rate
@@ -166,7 +168,9 @@ int hs_whiten(hs_ctx *ctx, const float *strain, int64_t n, double fs, double f_l
  *   spectra_out device (element size 8 for F32, 4 otherwise);
  *   k_lo_out, k_hi_out, rho2_scale_out, sigma_out device [n_tmpl];
  *   chisq_edges_out device int32 [n_tmpl][p + 1] (NULL when chisq_bins == 0).
- * HS_EINVAL if a band is empty or k1 >= k0 is violated, or chisq_bins is 1 or > 16.
+ * HS_EINVAL if a band is empty or k1 >= k0 is violated, chisq_bins is 1 or > 16,
+ * the PSD is not positive and finite inside a band, or a template has no
+ * (or non-finite) power inside its band.
  */
 int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, const double *psd,
                     int32_t n_tmpl, const void *raw, const int64_t *offset, const int32_t *k0,

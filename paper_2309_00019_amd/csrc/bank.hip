@@ -39,12 +39,15 @@ __global__ __launch_bounds__(256) void prepare_bank_kernel(
         return;
     }
     double sum = 0.0, mx = 0.0;
+    bool psd_ok = true;
     for (int64_t k = lo + tid; k <= hi; k += 256) {
         const float2 h = raw[off + (k - a0)];
+        psd_ok = psd_ok && psd[k] > 0.0 && psd[k] < INFINITY;
         const double a2 = ((double)h.x * (double)h.x + (double)h.y * (double)h.y) / psd[k];
         sum += a2;
         mx = fmax(mx, a2);
     }
+    if (!psd_ok) atomicOr(bad, 2);
     s_sum[tid] = sum;
     s_max[tid] = mx;
     __syncthreads();
@@ -54,6 +57,18 @@ __global__ __launch_bounds__(256) void prepare_bank_kernel(
             s_max[tid] = fmax(s_max[tid], s_max[tid + o]);
         }
         __syncthreads();
+    }
+    // a template with no power in its band (or a non-finite one) has no normalisation
+    if (!(s_sum[0] > 0.0 && s_sum[0] < INFINITY)) {
+        if (tid == 0) {
+            atomicOr(bad, 4);
+            klo_out[t] = lo;
+            khi_out[t] = hi;
+            r2s_out[t] = 0.0f;
+            sigma_out[t] = 0.0;
+        }
+        for (int64_t k = a0 + tid; k <= a1; k += 256) out[off + (k - a0)] = ST::pack(0.0f, 0.0f);
+        return;
     }
     const double sigma = sqrt(4.0 * df * s_sum[0]);
     const double norm = 4.0 * df / sigma;
@@ -126,6 +141,11 @@ __global__ __launch_bounds__(256) void chisq_edges_kernel(int64_t n, int32_t kf,
     const double prev = tid > 0 ? sc[tid - 1] : 0.0;
     const double total = sc[255];
     int32_t *e = edges + (int64_t)t * (p + 1);
+    if (!(total > 0.0 && total < INFINITY)) {  // flagged by the preparation kernel; edges stay defined
+        if (tid == 0)
+            for (int l = 0; l <= p; ++l) e[l] = (int32_t)(lo + (K * l) / p);
+        return;
+    }
     for (int l = 1; l < p; ++l) {
         const double T = (double)l * total / (double)p;
         if (!(prev <= T && T < next)) continue;
@@ -196,6 +216,8 @@ extern "C" int hs_prepare_bank(hs_ctx *ctx, int64_t n, double fs, double f_low, 
     }
     int32_t hbad = 0;
     HS_TRY(read_back(ctx, bad, &hbad, sizeof(hbad)));
-    HS_REQUIRE(hbad == 0, "hs_prepare_bank: a template has an empty band or k1 < k0 / k_lo < k0");
+    HS_REQUIRE((hbad & 1) == 0, "hs_prepare_bank: a template has an empty band or k1 < k0 / k_lo < k0");
+    HS_REQUIRE((hbad & 2) == 0, "hs_prepare_bank: the PSD is not positive and finite inside a template band");
+    HS_REQUIRE((hbad & 4) == 0, "hs_prepare_bank: a template has no (or non-finite) power inside its band");
     return HS_OK;
 }

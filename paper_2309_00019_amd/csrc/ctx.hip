@@ -381,8 +381,10 @@ int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (const char *s = std::getenv("HS_MF_BATCH_MB")) {
-        long v = std::atol(s);
-        if (v > 0) c->mf_batch_bytes = size_t(v) << 20;
+        // a whole number of MiB in the range hs_set_mf_batch_bytes accepts; anything else is ignored
+        char *end = nullptr;
+        const long v = std::strtol(s, &end, 10);
+        if (end != s && *end == 0 && v >= 1 && v <= (long(1) << 16)) c->mf_batch_bytes = size_t(v) << 20;
     }
     *ctx = c;
     hs::g_err[0] = 0;

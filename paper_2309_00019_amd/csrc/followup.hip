@@ -95,7 +95,8 @@ static int followup_impl(hs_ctx *ctx, const hs_coinc *c, int64_t n_c, float rho_
     HS_REQUIRE(ctx && n_ids, "hs_followup: null argument");
     HS_REQUIRE(n_c >= 0 && n_coarse >= 0 && n_fine >= 0 && n_seg >= 0 && seg_ticks > 0 && frac >= 0,
                "hs_followup: bad sizes");
-    HS_REQUIRE(n_c < (int64_t(1) << 32) && (int64_t)n_seg * n_fine < (int64_t(1) << 32),
+    HS_REQUIRE(n_c < (int64_t(1) << 32) && (int64_t)n_seg * n_fine < (int64_t(1) << 32) &&
+                   (double)n_c * (double)n_fine < 9.0e18,
                "hs_followup: input too large");
     for (int s = 0; s < n_seg; ++s) n_ids[s] = 0;
     if (n_seg == 0 || n_fine == 0 || n_c == 0) return HS_OK;

@@ -186,8 +186,11 @@ def mf_batch_templates(n: int, n_ids: int, ctx: "Context" = None) -> int:
     if ctx is not None:
         budget = hs_get_mf_batch_bytes(ctx)
     else:
-        mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
-        budget = (mb << 20) if mb > 0 else (128 << 20)
+        try:
+            mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
+        except ValueError:
+            mb = 0
+        budget = (mb << 20) if 1 <= mb <= (1 << 16) else (128 << 20)
     return max(1, min(65535, n_ids, budget // (n * 8)))
 
 

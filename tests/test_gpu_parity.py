@@ -87,6 +87,37 @@ def test_prepare_bank_sigma_and_band(ctx, dtype):
         assert abs(sig[t] / ref - 1) < 1e-12
 
 
+def test_prepare_bank_rejects_unnormalisable_templates(ctx):
+    """sigma = 0 (no power in the band) or a PSD that is not positive inside a band leaves
+    Eq. (2)'s normalisation undefined: the call reports HS_EINVAL instead of writing NaNs."""
+    import torch
+    from paper_2309_00019_amd import hs
+    _say("prepare_bank rejects")
+    n, fs, f_low = 2 ** 13, 512.0, 30.0
+    bank = _bank_for("eq", n, fs, f_low)
+    psd = analytic_psd(n, fs)
+    dev = ctx.device
+    off = torch.as_tensor(bank.offset, device=dev)
+    k0 = torch.as_tensor(bank.k0, device=dev)
+    ks = torch.as_tensor(bank.kstart, device=dev)
+    k1 = torch.as_tensor(bank.k1, device=dev)
+    raw = bank.data.copy()
+    raw[bank.offset[3]:bank.offset[3] + (bank.k1[3] - bank.k0[3] + 1)] = 0
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_prepare_bank(ctx, n, fs, f_low, torch.as_tensor(psd, device=dev), torch.as_tensor(raw, device=dev),
+                           off, k0, ks, k1, "f32", chisq_bins=8)
+    assert e.value.status == hs.HS_EINVAL and "no (or non-finite) power" in str(e.value)
+    bad_psd = psd.copy()
+    bad_psd[oracle.band_edges(n, fs, f_low, bank.kstart[0], bank.k1[0])[0] + 5] = 0.0
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_prepare_bank(ctx, n, fs, f_low, torch.as_tensor(bad_psd, device=dev),
+                           torch.as_tensor(bank.data, device=dev), off, k0, ks, k1, "f32")
+    assert e.value.status == hs.HS_EINVAL and "PSD" in str(e.value)
+    # the intact bank still prepares after the failed calls
+    pb = device_bank(ctx, bank, torch.as_tensor(psd, device=dev), f_low)
+    assert np.all(pb.sigma.cpu().numpy() > 0)
+
+
 # ------------------------------------------------------------------------------------------
 # a3: complex SNR series (full) against the oracle
 # ------------------------------------------------------------------------------------------
