@@ -5,12 +5,15 @@
 // |m' - m| <= W has rho2' < rho2, or rho2' == rho2 and m' > m.  Ranking uses the 64-bit key
 // (float bits of rho2) << 32 | (2^32 - 1 - m), whose order is exactly that rule (rho2 >= 0).
 //
-// Work is O(candidates) and needs no sort: time is cut into tiles of exactly W samples.  Two
-// candidates in one tile are within W of each other, so only a tile's key maximum (its champion,
-// found with one atomicMax per candidate) can survive; the window of a champion in tile b lies
-// inside tiles b-1, b, b+1, so the champion only scans the candidates binned to its two
-// neighbour tiles.  Survivors occupy at most one slot per (template, tile); compacting the slots
-// in bin order yields triggers sorted by (template position, m) with no sort.
+// Work is O(candidates) and needs no sort and no per-tile lists: time is cut into tiles of
+// exactly W samples.  Two candidates in one tile are within W of each other, so only a tile's key
+// maximum (its champion, found with a 64-bit atomicMax) can survive, and a champion's window lies
+// inside its own tile and the two neighbouring ones.  The champion of tile b therefore survives
+// iff no candidate of tile b - 1 or b + 1 within W of it has a larger key, and every candidate can
+// check that itself against the champions of its two neighbour tiles (the champion's m is the low
+// half of its key), marking the ones it beats.  Survivors occupy at most one slot per
+// (template, tile); compacting the slots in bin order yields triggers sorted by (template
+// position, m) with no sort.
 #include "hs_internal.h"
 
 namespace hs {
@@ -19,57 +22,74 @@ __device__ __forceinline__ uint64_t cand_key(float rho2, int32_t m) {
     return ((uint64_t)__float_as_uint(rho2) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)m);
 }
 
-__global__ void clu_bin(const hs_candidate *__restrict__ cand, int64_t n_cand, int32_t n_ids, int64_t n,
-                        int64_t W, int64_t n_tiles, uint32_t *__restrict__ cnt, unsigned long long *__restrict__ best,
-                        int32_t *__restrict__ bad) {
+__device__ __forceinline__ int64_t key_m(uint64_t key) { return (int64_t)(0xFFFFFFFFu - (uint32_t)key); }
+
+__device__ __forceinline__ bool cand_ok(const hs_candidate &c, int32_t n_ids, int64_t n) {
+    return c.tpos >= 0 && c.tpos < n_ids && c.m >= 0 && (int64_t)c.m < n;
+}
+
+// Tile champions.  Candidates arrive in runs that share a bin (the filter writes each row's
+// candidates in sample order), so a wavefront first takes the maximum over each run of equal bins
+// (a segmented scan with shuffles; the bins are below 2^28) and only a run's last lane issues the
+// atomic, and only when the bin's current value does not already beat it (values only grow, so a
+// stale read, atomic like the updates, can only let a useless atomic through).
+__global__ __launch_bounds__(256) void clu_best(const hs_candidate *__restrict__ cand, int64_t n_cand,
+                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles,
+                                                unsigned long long *__restrict__ best, int32_t *__restrict__ bad) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n_cand) return;
-    const hs_candidate c = cand[i];
-    if (c.tpos < 0 || c.tpos >= n_ids || c.m < 0 || (int64_t)c.m >= n) {
-        atomicOr(bad, 1);
-        return;
+    int32_t b = -1;
+    unsigned long long k = 0;
+    if (i < n_cand) {
+        const hs_candidate c = cand[i];
+        if (cand_ok(c, n_ids, n)) {
+            b = (int32_t)((int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W);
+            k = cand_key(c.rho2, c.m);
+        } else {
+            atomicOr(bad, 1);
+        }
     }
-    const int64_t b = (int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W;
-    atomicAdd(&cnt[b], 1u);
-    atomicMax(&best[b], (unsigned long long)cand_key(c.rho2, c.m));
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const int32_t bu = __shfl_up(b, s);
+        const unsigned long long ku = __shfl_up(k, s);
+        if (lane >= s && bu == b && ku > k) k = ku;
+    }
+    const int32_t bn = __shfl_down(b, 1);
+    const bool tail = lane == 63 || bn != b;
+    if (tail && b >= 0 && __hip_atomic_load(&best[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k)
+        atomicMax(&best[b], k);
 }
 
-__global__ void clu_scatter(const hs_candidate *__restrict__ cand, int64_t n_cand, int32_t n_ids, int64_t n,
-                            int64_t W, int64_t n_tiles, const uint64_t *__restrict__ start,
-                            uint32_t *__restrict__ cursor, uint32_t *__restrict__ lists) {
+// Champion slots and vetoes: the candidate holding its bin's maximum records its index; every
+// candidate marks the champion of a neighbour tile that lies within W and has a smaller key.
+__global__ __launch_bounds__(256) void clu_veto(const hs_candidate *__restrict__ cand, int64_t n_cand,
+                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles,
+                                                const unsigned long long *__restrict__ best,
+                                                uint32_t *__restrict__ slot, uint32_t *__restrict__ veto) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n_cand) return;
     const hs_candidate c = cand[i];
-    if (c.tpos < 0 || c.tpos >= n_ids || c.m < 0 || (int64_t)c.m >= n) return;
-    const int64_t b = (int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W;
-    const uint32_t p = atomicAdd(&cursor[b], 1u);
-    lists[start[b] + p] = (uint32_t)i;
-}
-
-__global__ void clu_champion(const hs_candidate *__restrict__ cand, int64_t n_cand, int32_t n_ids, int64_t n,
-                             int64_t W, int64_t n_tiles, const uint64_t *__restrict__ start,
-                             const uint32_t *__restrict__ lists, const unsigned long long *__restrict__ best,
-                             uint32_t *__restrict__ flag, uint32_t *__restrict__ slot) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n_cand) return;
-    const hs_candidate c = cand[i];
-    if (c.tpos < 0 || c.tpos >= n_ids || c.m < 0 || (int64_t)c.m >= n) return;
+    if (!cand_ok(c, n_ids, n)) return;
     const int64_t tile = (uint32_t)c.m / (uint32_t)W;
     const int64_t b = (int64_t)c.tpos * n_tiles + tile;
     const uint64_t key = cand_key(c.rho2, c.m);
-    if (key != best[b]) return;
+    if (key == best[b]) slot[b] = (uint32_t)i;
     for (int d = -1; d <= 1; d += 2) {
         const int64_t nt = tile + d;
         if (nt < 0 || nt >= n_tiles) continue;
-        const int64_t nb = b + d;
-        for (uint64_t p = start[nb]; p < start[nb + 1]; ++p) {
-            const hs_candidate o = cand[lists[p]];
-            const int64_t dm = (int64_t)o.m - (int64_t)c.m;
-            if ((dm <= W && dm >= -W) && cand_key(o.rho2, o.m) > key) return;
-        }
+        const uint64_t kb = best[b + d];
+        if (kb == 0 || kb >= key) continue;  // empty tile (keys are never 0) or a better champion
+        const int64_t dm = key_m(kb) - (int64_t)c.m;
+        if (dm <= W && dm >= -W) veto[b + d] = 1u;
     }
-    flag[b] = 1u;
-    slot[b] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void clu_flag(const unsigned long long *__restrict__ best,
+                                                const uint32_t *__restrict__ veto, int64_t bins,
+                                                uint32_t *__restrict__ flag) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < bins) flag[b] = (best[b] != 0 && veto[b] == 0) ? 1u : 0u;
 }
 
 __global__ void clu_emit(const hs_candidate *__restrict__ cand, int64_t bins, const uint32_t *__restrict__ flag,
@@ -114,40 +134,33 @@ extern "C" int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_
     const int64_t bins = (int64_t)n_ids * n_tiles;
     HS_REQUIRE(bins <= (int64_t(1) << 28), "hs_cluster_triggers: %lld (template, tile) bins exceed 2^28; "
                "use a wider window", (long long)bins);
-    uint32_t *cnt, *cursor, *lists, *flag, *slot;
+    uint32_t *veto, *flag, *slot;
     unsigned long long *best;
-    uint64_t *start, *off, *tmp;
+    uint64_t *off, *tmp;
     int32_t *bad;
     Carver cv;
-    cv.add(&cnt, bins);
-    cv.add(&cursor, bins);
+    cv.add(&veto, bins);
     cv.add(&flag, bins);
     cv.add(&slot, bins);
     cv.add(&best, bins);
-    cv.add(&start, bins + 1);
     cv.add(&off, bins + 1);
     cv.add(&tmp, scan_tmp_elems(bins));
-    cv.add(&lists, n_cand);
     cv.add(&bad, 1);
     HS_TRY(cv.commit(ctx));
-    HS_TRY(fill_u32(ctx, cnt, bins, 0));
-    HS_TRY(fill_u32(ctx, cursor, bins, 0));
-    HS_TRY(fill_u32(ctx, flag, bins, 0));
+    HS_TRY(fill_u32(ctx, veto, bins, 0));
     HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(best), bins, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
     const unsigned gc = (unsigned)cdiv(n_cand, 256);
-    hipLaunchKernelGGL(clu_bin, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, cnt,
-                       best, bad);
-    HS_HIP(hipGetLastError());
-    HS_TRY(exclusive_scan_u32(ctx, cnt, bins, start, tmp));
-    hipLaunchKernelGGL(clu_scatter, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles,
-                       start, cursor, lists);
-    hipLaunchKernelGGL(clu_champion, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles,
-                       start, lists, best, flag, slot);
+    const unsigned gb = (unsigned)cdiv(bins, 256);
+    hipLaunchKernelGGL(clu_best, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, best,
+                       bad);
+    hipLaunchKernelGGL(clu_veto, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, best,
+                       slot, veto);
+    hipLaunchKernelGGL(clu_flag, dim3(gb), dim3(256), 0, ctx->stream, best, veto, bins, flag);
     HS_HIP(hipGetLastError());
     HS_TRY(exclusive_scan_u32(ctx, flag, bins, off, tmp));
-    hipLaunchKernelGGL(clu_emit, dim3((unsigned)cdiv(bins, 256)), dim3(256), 0, ctx->stream, cand, bins, flag, slot,
-                       off, tmpl_ids, seg, seg_t0, ticks_per_sample, out, cap);
+    hipLaunchKernelGGL(clu_emit, dim3(gb), dim3(256), 0, ctx->stream, cand, bins, flag, slot, off, tmpl_ids, seg,
+                       seg_t0, ticks_per_sample, out, cap);
     HS_HIP(hipGetLastError());
     uint64_t total = 0;
     int32_t hbad = 0;
