@@ -12,9 +12,9 @@
 // (tmpl, tick_h, tick_l)) reuses the tile idea of trigger clustering: bins are (slide, tile of
 // W_c ticks of tick_h); a bin's best member is found with a 64-bit atomicMax on
 // (stat bits, 0xFFFF - tmpl, 0xFFFF - tick_h offset in the tile) plus an atomicMin on tick_l for
-// exact ties; only that champion can survive, and it checks the neighbouring tiles of its slide
-// (against their champions first, scanning a tile's members only when its better champion lies
-// out of reach).
+// exact ties; only that champion can survive, and since the key and the tie value describe it
+// completely, every coincidence checks the champions of the neighbouring tiles of its slide
+// itself and marks those it beats within reach (no per-bin lists).
 // Survivors are compacted in bin order, i.e. sorted by (slide, tick_h).
 #include <algorithm>
 #include <cmath>
@@ -146,16 +146,18 @@ __device__ __forceinline__ int64_t coinc_bin(const RawCoinc &r, int64_t tick_h, 
     return (int64_t)r.k * bg.n_tiles + *tile;
 }
 
+// Bin champions (a read first skips the atomic when the bin already holds a larger key; values
+// only grow, so a stale read can only let a useless atomic through).
 __global__ void co_bin(const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h,
-                       BinGeom bg, uint32_t *__restrict__ cnt, unsigned long long *__restrict__ best) {
+                       BinGeom bg, unsigned long long *__restrict__ best) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= P) return;
     const RawCoinc r = raw[q];
     const hs_trigger a = h[r.i];
     int64_t tile;
     const int64_t b = coinc_bin(r, a.tick, bg, &tile);
-    atomicAdd(&cnt[b], 1u);
-    atomicMax(&best[b], (unsigned long long)coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw));
+    const unsigned long long key = coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw);
+    if (__hip_atomic_load(&best[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < key) atomicMax(&best[b], key);
 }
 
 __global__ void co_bin_tie(const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h,
@@ -171,17 +173,6 @@ __global__ void co_bin_tie(const RawCoinc *__restrict__ raw, int64_t P, const hs
         atomicMin(&best_tl[b], (unsigned long long)l[r.j].tick);
 }
 
-__global__ void co_scatter(const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h,
-                           BinGeom bg, const uint64_t *__restrict__ start, uint32_t *__restrict__ cursor,
-                           uint32_t *__restrict__ lists) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= P) return;
-    const RawCoinc r = raw[q];
-    int64_t tile;
-    const int64_t b = coinc_bin(r, h[r.i].tick, bg, &tile);
-    lists[start[b] + atomicAdd(&cursor[b], 1u)] = (uint32_t)q;
-}
-
 // true iff coincidence (s2, tm2, th2, tl2) is better than (s1, tm1, th1, tl1)
 __device__ __forceinline__ bool coinc_better(float s2, int32_t tm2, int64_t th2, int64_t tl2, float s1, int32_t tm1,
                                              int64_t th1, int64_t tl1) {
@@ -191,97 +182,56 @@ __device__ __forceinline__ bool coinc_better(float s2, int32_t tm2, int64_t th2,
     return tl2 < tl1;
 }
 
-// Per coincidence: only the champion of its bin can survive; it checks the neighbouring tiles of
-// its slide.  A neighbour bin's champion is its best member in the same order, so if it is not
-// better no member is, and if it is better and within reach this one loses.  Only a better
-// champion out of reach leaves the bin's members to scan; those scans are done by the whole
-// wavefront, 64 members at a time, one pending scan after another (a glitch can put thousands
-// of same-slide pairs into one bin, too many for one lane).
-__global__ __launch_bounds__(256) void co_champion(
-    const RawCoinc *__restrict__ raw, int64_t P, const hs_trigger *__restrict__ h, const hs_trigger *__restrict__ l,
-    BinGeom bg, int64_t wrap, const unsigned long long *__restrict__ best,
-    const unsigned long long *__restrict__ best_tl, const uint64_t *__restrict__ start,
-    const uint32_t *__restrict__ lists, uint32_t *__restrict__ flag, uint32_t *__restrict__ slot) {
+// Only the champion of a bin can survive (its members lie within W_c of each other), and a
+// bin's champion is fully described by its key and tie value.  Per coincidence: the bin's
+// champion records its index; every coincidence compares itself with the champions of the
+// neighbouring tiles of its slide (circular offsets -2..2, distinct, excluding its own tile: the
+// last tile may be partial, so a reach of W_c can span two tiles across the wrap) and marks those
+// it beats within reach.
+__global__ __launch_bounds__(256) void co_veto(const RawCoinc *__restrict__ raw, int64_t P,
+                                               const hs_trigger *__restrict__ h, const hs_trigger *__restrict__ l,
+                                               BinGeom bg, int64_t wrap, const unsigned long long *__restrict__ best,
+                                               const unsigned long long *__restrict__ best_tl,
+                                               uint32_t *__restrict__ slot, uint32_t *__restrict__ veto) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool champ = false, lose = false;
-    RawCoinc r{0, 0, 0, 0.0f};
-    hs_trigger a{};
-    int64_t tl = 0, b = 0, tile = 0;
-    int64_t pend[4] = {0, 0, 0, 0};
-    int npend = 0;
-    if (q < P) {
-        r = raw[q];
-        a = h[r.i];
-        tl = l[r.j].tick;
-        b = coinc_bin(r, a.tick, bg, &tile);
-        champ = coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw) == best[b] && (unsigned long long)tl == best_tl[b];
-    }
-    if (champ) {
-        const int64_t nt = bg.n_tiles;
-        const int64_t slide0 = (int64_t)r.k * nt;
-        // neighbour tiles at circular offsets -2..2 (distinct, excluding this tile)
-        int64_t seen[4];
-        int ns = 0;
-        for (int dd = -2; dd <= 2 && !lose; ++dd) {
-            if (dd == 0) continue;
-            const int64_t t2 = pos_mod(tile + dd, nt);
-            if (t2 == tile) continue;
-            bool dup = false;
-            for (int u = 0; u < ns; ++u) dup |= (seen[u] == t2);
-            if (dup) continue;
-            seen[ns++] = t2;
-            const int64_t nb = slide0 + t2;
-            if (start[nb] == start[nb + 1]) continue;
-            const unsigned long long kb = best[nb];
-            const float s2 = __uint_as_float((uint32_t)(kb >> 32));
-            const int32_t tm2 = 0xFFFF - (int32_t)((kb >> 16) & 0xFFFF);
-            const int64_t th2 = t2 * bg.cw + (0xFFFF - (int64_t)(kb & 0xFFFF));
-            const int64_t tl2 = (int64_t)best_tl[nb];
-            if (!coinc_better(s2, tm2, th2, tl2, r.stat, a.tmpl, a.tick, tl)) continue;
-            int64_t d2 = pos_mod(th2 - a.tick + wrap / 2, wrap) - wrap / 2;
-            if (d2 < 0) d2 = -d2;
-            if (d2 <= bg.cw) {
-                lose = true;
-                break;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (u == npend) pend[u] = nb;
-            ++npend;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        uint64_t want = __ballot(champ && !lose && u < npend);
-        while (want) {
-            const int src = __ffsll((unsigned long long)want) - 1;
-            want &= want - 1;
-            const int64_t nb = __shfl(pend[u], src);
-            const int64_t th = __shfl(a.tick, src);
-            const int64_t tls = __shfl(tl, src);
-            const float st = __shfl(r.stat, src);
-            const int32_t tm = __shfl(a.tmpl, src);
-            const uint64_t p0 = start[nb], p1 = start[nb + 1];
-            bool found = false;
-            for (uint64_t p = p0; p < p1; p += 64) {
-                if (p + lane < p1) {
-                    const RawCoinc o = raw[lists[p + lane]];
-                    const hs_trigger oa = h[o.i];
-                    int64_t d = pos_mod(oa.tick - th + wrap / 2, wrap) - wrap / 2;
-                    if (d < 0) d = -d;
-                    found = d <= bg.cw && coinc_better(o.stat, oa.tmpl, oa.tick, l[o.j].tick, st, tm, th, tls);
-                }
-                if (__ballot(found)) break;
-            }
-            const bool any = __ballot(found) != 0;  // every lane takes part in the vote
-            if (lane == src && any) lose = true;
-        }
-    }
-    if (champ && !lose) {
-        flag[b] = 1u;
+    if (q >= P) return;
+    const RawCoinc r = raw[q];
+    const hs_trigger a = h[r.i];
+    const int64_t tl = l[r.j].tick;
+    int64_t tile;
+    const int64_t b = coinc_bin(r, a.tick, bg, &tile);
+    if (coinc_key(r.stat, a.tmpl, a.tick - tile * bg.cw) == best[b] && (unsigned long long)tl == best_tl[b])
         slot[b] = (uint32_t)q;
+    const int64_t nt = bg.n_tiles;
+    const int64_t slide0 = (int64_t)r.k * nt;
+    int64_t seen[4];
+    int ns = 0;
+    for (int dd = -2; dd <= 2; ++dd) {
+        if (dd == 0) continue;
+        const int64_t t2 = pos_mod(tile + dd, nt);
+        if (t2 == tile) continue;
+        bool dup = false;
+        for (int u = 0; u < ns; ++u) dup |= (seen[u] == t2);
+        if (dup) continue;
+        seen[ns++] = t2;
+        const int64_t nb = slide0 + t2;
+        const unsigned long long kb = best[nb];
+        if (kb == 0) continue;  // empty bin (a key's low 16 bits are never 0)
+        const float s2 = __uint_as_float((uint32_t)(kb >> 32));
+        const int32_t tm2 = 0xFFFF - (int32_t)((kb >> 16) & 0xFFFF);
+        const int64_t th2 = t2 * bg.cw + (0xFFFF - (int64_t)(kb & 0xFFFF));
+        if (!coinc_better(r.stat, a.tmpl, a.tick, tl, s2, tm2, th2, (int64_t)best_tl[nb])) continue;
+        int64_t d2 = pos_mod(th2 - a.tick + wrap / 2, wrap) - wrap / 2;
+        if (d2 < 0) d2 = -d2;
+        if (d2 <= bg.cw) veto[nb] = 1u;
     }
+}
+
+__global__ __launch_bounds__(256) void co_flag(const unsigned long long *__restrict__ best,
+                                               const uint32_t *__restrict__ veto, int64_t bins,
+                                               uint32_t *__restrict__ flag) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < bins) flag[b] = (best[b] != 0 && veto[b] == 0) ? 1u : 0u;
 }
 
 __global__ void co_emit(const RawCoinc *__restrict__ raw, const hs_trigger *__restrict__ h,
@@ -407,9 +357,9 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     // Phase-1 buffers are re-carved first, in the same order, so they keep their contents
     // (arena growth preserves what was written).
     RawCoinc *raw;
-    uint32_t *bcnt, *bcur, *lists, *flag, *slot;
+    uint32_t *veto, *flag, *slot;
     unsigned long long *best, *best_tl, *bgc;
-    uint64_t *bstart, *boff, *tmp2;
+    uint64_t *boff, *tmp2;
     double *e2;
     {
         Carver cv;
@@ -422,16 +372,13 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         cv.add(&tmp1, scan_tmp_elems(nh > n_tmpl ? nh : n_tmpl));
         cv.add(&bad, 1);
         cv.add(&raw, P);
-        cv.add(&bcnt, bins);
-        cv.add(&bcur, bins);
+        cv.add(&veto, bins);
         cv.add(&flag, bins);
         cv.add(&slot, bins);
         cv.add(&best, bins);
         cv.add(&best_tl, bins);
-        cv.add(&bstart, bins + 1);
         cv.add(&boff, bins + 1);
-        cv.add(&tmp2, scan_tmp_elems(bins > (int64_t)P ? bins : (int64_t)P));
-        cv.add(&lists, P);
+        cv.add(&tmp2, scan_tmp_elems(bins));
         cv.add(&e2, n_edges > 0 ? n_edges : 1);
         cv.add(&bgc, n_edges + 1);
         HS_TRY(cv.commit(ctx));
@@ -439,19 +386,15 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     hipLaunchKernelGGL(co_pair_write, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l, n_tmpl, g,
                        lstart, lidx, poff, raw);
     HS_HIP(hipGetLastError());
-    HS_TRY(fill_u32(ctx, bcnt, bins, 0));
-    HS_TRY(fill_u32(ctx, bcur, bins, 0));
-    HS_TRY(fill_u32(ctx, flag, bins, 0));
+    HS_TRY(fill_u32(ctx, veto, bins, 0));
     HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(best), bins, 0));
     HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(best_tl), bins, ~uint64_t(0)));
     const unsigned gp = (unsigned)cdiv((int64_t)P, 256);
-    hipLaunchKernelGGL(co_bin, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, bgm, bcnt, best);
+    hipLaunchKernelGGL(co_bin, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, bgm, best);
     hipLaunchKernelGGL(co_bin_tie, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, l, bgm, best, best_tl);
-    HS_HIP(hipGetLastError());
-    HS_TRY(exclusive_scan_u32(ctx, bcnt, bins, bstart, tmp2));
-    hipLaunchKernelGGL(co_scatter, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, bgm, bstart, bcur, lists);
-    hipLaunchKernelGGL(co_champion, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, l, bgm, wrap, best,
-                       best_tl, bstart, lists, flag, slot);
+    hipLaunchKernelGGL(co_veto, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, h, l, bgm, wrap, best, best_tl,
+                       slot, veto);
+    hipLaunchKernelGGL(co_flag, dim3((unsigned)cdiv(bins, 256)), dim3(256), 0, ctx->stream, best, veto, bins, flag);
     HS_HIP(hipGetLastError());
     HS_TRY(exclusive_scan_u32(ctx, flag, bins, boff, tmp2));
     hipLaunchKernelGGL(co_emit, dim3((unsigned)cdiv(bins, 256)), dim3(256), 0, ctx->stream, raw, h, l, bins, flag, slot,
