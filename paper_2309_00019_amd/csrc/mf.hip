@@ -13,10 +13,11 @@
 // loading (only bins inside the template's band are read), and pass B ends with the threshold
 // and a wavefront-ballot compaction: one atomic per wavefront that holds candidates.
 //
-// Pass A: a 256-thread workgroup owns 16 consecutive columns k1 of one template; thread
-// (c = tid % 16, l = tid / 16) loads x[l + 16 j], j < 16, of column c (16 lanes read 128
-// contiguous bytes of spectrum per row), does a radix-16 DFT over j in registers, exchanges
-// through LDS, and a second radix-16 DFT finishes each 256-point transform.
+// Pass A: a workgroup of 16 x COLS threads owns COLS consecutive columns k1 of one template
+// (COLS = 64, or 16 for N1 < 64); thread (c = tid % COLS, l = tid / COLS) loads x[l + 16 j],
+// j < 16, of column c (COLS lanes read 8 COLS contiguous bytes of spectrum per row), does a
+// radix-16 DFT over j in registers, exchanges through LDS, and a second radix-16 DFT finishes
+// each 256-point transform; every row of the intermediate is written in pieces of 8 COLS bytes.
 // Pass B: each lane holds 16 points of a row; N1/16 lanes share a row; radix-16 passes with
 // LDS exchanges (Stockham indexing), the last pass ending in registers for the epilogue.
 // Both passes are bound by latency more than by bandwidth (a few workgroups per CU, LDS-limited),
@@ -33,7 +34,10 @@
 
 namespace hs {
 
-static constexpr int PA_LDS_LSTRIDE = 16 * 16 + 16;  // float2 per l-block (padded by 16)
+// Pass-A columns per workgroup: 64 where N1 allows (each row of the intermediate is then written
+// in 512-byte pieces; 16 columns, i.e. 128-byte pieces, ran 4-5 % slower per template and 8
+// columns 43 %), else 16.  The exchange buffer holds 16 l-blocks of 16 x COLS values, padded.
+template <int COLS> constexpr int pa_lds_stride() { return COLS * 16 + COLS; }
 static constexpr int MF_STRIPES = 64;                 // candidate lists (power of two)
 
 // Candidate lists: MF_STRIPES lists of stripe_cap records followed by one spill list of
@@ -98,18 +102,19 @@ __global__ void mf_items(const int32_t *__restrict__ ids, int32_t n_ids, int32_t
     items[i] = it;
 }
 
-// 256 threads, at least 4 waves per SIMD (caps VGPRs at 128 so 4 workgroups fit a CU).
-template <typename ST>
-__global__ __launch_bounds__(256, 4) void mf_pass_a(
+// 16 x COLS threads; 1024 threads per CU, i.e. 4 waves per SIMD (caps VGPRs at 128).
+template <typename ST, int COLS>
+__global__ __launch_bounds__(16 * COLS, 64 / COLS) void mf_pass_a(
     const float2 *__restrict__ dspec, const typename ST::elem *__restrict__ spectra,
     const MfItem *__restrict__ items, int32_t id0, int32_t N1, const float2 *__restrict__ tw512,
     const float2 *__restrict__ twlo, const float2 *__restrict__ twhi, float2 *__restrict__ Y) {
-    __shared__ float2 lds[16 * PA_LDS_LSTRIDE];
+    constexpr int LSTRIDE = pa_lds_stride<COLS>();
+    __shared__ float2 lds[16 * LSTRIDE];
     const int tb = blockIdx.y;
     const MfItem it = items[id0 + tb];
-    const int c = threadIdx.x & 15;
-    const int l = threadIdx.x >> 4;
-    const int k1 = blockIdx.x * 16 + c;
+    const int c = threadIdx.x % COLS;
+    const int l = threadIdx.x / COLS;
+    const int k1 = blockIdx.x * COLS + c;
     const int64_t base = it.base;
     const int lo = it.lo, hi = it.hi;
 
@@ -177,12 +182,12 @@ __global__ __launch_bounds__(256, 4) void mf_pass_a(
         }
         if (r) __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 16; ++a) lds[l * PA_LDS_LSTRIDE + a * 16 + c] = v[a];
+        for (int a = 0; a < 16; ++a) lds[l * LSTRIDE + a * COLS + c] = v[a];
         __syncthreads();
         const int a = l;
         float2 w[16];
 #pragma unroll
-        for (int l2 = 0; l2 < 16; ++l2) w[l2] = lds[l2 * PA_LDS_LSTRIDE + a * 16 + c];
+        for (int l2 = 0; l2 < 16; ++l2) w[l2] = lds[l2 * LSTRIDE + a * COLS + c];
         dft16<1>(w);  // w[b] = 256-point output a + 16 b
         const int j0 = k1 * (2 * a + r);  // < N
         float2 tw = cmul(twhi[j0 >> 10], twlo[j0 & 1023]);
@@ -430,6 +435,28 @@ static int launch_pass_b(hs_ctx *ctx, int N1, int tb, const float2 *Y, const MfI
     return HS_OK;
 }
 
+template <int COLS>
+static int launch_pass_a(hs_ctx *ctx, const hs_bank *bank, const float2 *d, const MfItem *items, int32_t id0,
+                         int32_t tb, int N1, const float2 *tw512, const float2 *twlo, const float2 *twhi, float2 *Y) {
+    const dim3 ga((unsigned)(N1 / COLS), (unsigned)tb), gt(16 * COLS);
+    switch (bank->dtype) {
+    case HS_F32:
+        hipLaunchKernelGGL((mf_pass_a<StoreF32, COLS>), ga, gt, 0, ctx->stream, d,
+                           static_cast<const float2 *>(bank->spectra), items, id0, N1, tw512, twlo, twhi, Y);
+        break;
+    case HS_BF16:
+        hipLaunchKernelGGL((mf_pass_a<StoreBF16, COLS>), ga, gt, 0, ctx->stream, d,
+                           static_cast<const uint32_t *>(bank->spectra), items, id0, N1, tw512, twlo, twhi, Y);
+        break;
+    default:
+        hipLaunchKernelGGL((mf_pass_a<StoreF16, COLS>), ga, gt, 0, ctx->stream, d,
+                           static_cast<const uint32_t *>(bank->spectra), items, id0, N1, tw512, twlo, twhi, Y);
+        break;
+    }
+    HS_HIP(hipGetLastError());
+    return HS_OK;
+}
+
 template <bool WRITE_Z>
 static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank, const int32_t *ids,
                   int32_t n_ids, float thr, hs_candidate *cand, int64_t cap, int64_t *n_cand, float2 *zout) {
@@ -490,26 +517,9 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     const float thr2 = thr * thr;
     for (int64_t id0 = 0; id0 < n_ids; id0 += tb_max) {
         const int32_t tb = (int32_t)((n_ids - id0) < tb_max ? (n_ids - id0) : tb_max);
-        const dim3 ga((unsigned)(N1 / 16), (unsigned)tb);
         const float2 *d = static_cast<const float2 *>(spec);
-        switch (bank->dtype) {
-        case HS_F32:
-            hipLaunchKernelGGL(mf_pass_a<StoreF32>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const float2 *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
-                               twhi, Y);
-            break;
-        case HS_BF16:
-            hipLaunchKernelGGL(mf_pass_a<StoreBF16>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const uint32_t *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
-                               twhi, Y);
-            break;
-        default:
-            hipLaunchKernelGGL(mf_pass_a<StoreF16>, ga, dim3(256), 0, ctx->stream, d,
-                               static_cast<const uint32_t *>(bank->spectra), items, (int32_t)id0, N1, tw512, twlo,
-                               twhi, Y);
-            break;
-        }
-        HS_HIP(hipGetLastError());
+        if (N1 >= 64) HS_TRY((launch_pass_a<64>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
+        else HS_TRY((launch_pass_a<16>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
         HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, tb, Y, items, (int32_t)id0, thr2, twN1, sbuf, counter, stripe_cap,
                                       spill_cap, zout));
     }
