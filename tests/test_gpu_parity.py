@@ -255,6 +255,34 @@ def test_cluster_exact_on_identical_inputs(ctx, seed, n, W):
     assert np.array_equal(got["phase"], ref["phase"].astype(np.float32))
 
 
+@pytest.mark.parametrize("order", ["sorted", "rows"])
+def test_cluster_exact_in_filter_order(ctx, order):
+    """Candidates arriving in long runs of one (template, tile) -- sorted by sample, or in the
+    filter's row order m = m2 + 512 m1 -- with dense clumps (every sample of several windows a
+    candidate) and plateaus of exactly equal rho2: the wavefront run maxima that thin the
+    champion atomics must leave the triggers exactly the oracle's."""
+    from paper_2309_00019_amd import hs
+    import torch
+    _say(f"cluster order={order}")
+    n, W = 2 ** 16, 256
+    g = np.random.default_rng(31)
+    cand = synth.synthetic_candidates(g, 5, n, 2000, 4.0, clumps=4, clump_len=6 * W, ties=50)
+    cand["rho2"][::7] = np.float32(20.0)
+    if order == "sorted":
+        cand = cand[np.lexsort((cand["m"], cand["tpos"]))]
+    else:
+        cand = cand[np.lexsort((cand["m"] // 512, cand["m"] % 512, cand["tpos"]))]
+    ids_h = np.arange(10, 15, dtype=np.int32)
+    out = hs.hs_cluster_triggers(ctx, hs.to_device_records(cand, ctx.device), n,
+                                 torch.as_tensor(ids_h, device=ctx.device), W, seg=0, seg_t0=0, ticks_per_sample=25)
+    got = hs.as_records(out, hs.TRIGGER)
+    ref = oracle.triggers_from_candidates(cand["tpos"], cand["m"], cand["rho2"], cand["phase"], ids_h, W, 0, 0, 25)
+    assert len(got) == len(ref["tick"]) > 0
+    assert np.array_equal(got["tmpl"], ref["tmpl"])
+    assert np.array_equal(got["tick"], ref["tick"])
+    assert np.array_equal(got["snr"], ref["snr"].astype(np.float32))
+
+
 # ------------------------------------------------------------------------------------------
 # a6: coincidence (identical trigger inputs -> exact)
 # ------------------------------------------------------------------------------------------
