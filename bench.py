@@ -53,9 +53,11 @@ def parse():
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--chunk", type=int, default=2048, help="templates generated per host chunk")
     ap.add_argument("--batch-mb", type=int, default=0,
-                    help="matched-filter intermediate budget in MB; 0 = measure it and the tile in set-up (autotuner)")
+                    help="matched-filter intermediate budget in MB; 0 = measure it and the tiles in set-up (autotuner)")
     ap.add_argument("--tile", type=int, default=128, choices=[64, 128, 256],
                     help="pass-B threads per workgroup when --batch-mb fixes the schedule")
+    ap.add_argument("--pa-cols", type=int, default=64, choices=[16, 32, 64],
+                    help="pass-A columns per workgroup when --batch-mb fixes the schedule")
     ap.add_argument("--only", choices=["both", "hier", "flat"], default="both",
                     help="restrict the run (profiling): hier = hierarchical + proposer only")
     ap.add_argument("--calib-copy", action="store_true",
@@ -196,7 +198,9 @@ def main():
     if args.batch_mb > 0:           # fixed schedule (counter runs, where the tracer distorts timing)
         hs.hs_set_mf_batch_bytes(ctx, args.batch_mb << 20)
         hs.hs_set_mf_tile(ctx, args.tile)
-        sched = {"batch_mb": args.batch_mb, "tile": args.tile, "budgets": {}, "tiles": {}}
+        hs.hs_set_mf_pa_cols(ctx, args.pa_cols)
+        sched = {"batch_mb": args.batch_mb, "tile": args.tile, "pa_cols": args.pa_cols, "budgets": {}, "tiles": {},
+                 "pa_tiles": {}}
     else:
         sched = autotune.tune_mf_schedule(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
     best_mb, tune_table = sched["batch_mb"], sched["budgets"]
@@ -355,6 +359,7 @@ def main():
                    "proposer_p_cum": prop.p_cum,
                    "mf_batch_mb": best_mb, "mf_autotune_us_per_template": tune_table,
                    "mf_tile_threads": sched["tile"], "mf_autotune_tile_us_per_template": sched["tiles"],
+                   "mf_pass_a_columns": sched["pa_cols"], "mf_autotune_pass_a_us_per_template": sched["pa_tiles"],
                    "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }

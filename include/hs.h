@@ -120,6 +120,15 @@ int64_t hs_get_mf_batch_bytes(const hs_ctx *ctx);
 int hs_set_mf_tile(hs_ctx *ctx, int32_t pass_b_threads);
 int32_t hs_get_mf_tile(const hs_ctx *ctx);
 
+/* Matched-filter tile of the first pass: columns k1 per pass-A workgroup, 16, 32
+ * or 64 (default); a workgroup of 16 x cols threads transforms cols columns of
+ * 512 points and writes each row of the intermediate in pieces of 8 cols bytes
+ * (capped at N1 = n/512 columns).  Results do not depend on it; set by the
+ * autotuner.  HS_EINVAL for other values.  hs_get_mf_pa_cols returns the
+ * current value (0 for a NULL context). */
+int hs_set_mf_pa_cols(hs_ctx *ctx, int32_t cols);
+int32_t hs_get_mf_pa_cols(const hs_ctx *ctx);
+
 /*
  * One-sided Welch PSD (the weight S_n of Eq. (2); the paper does not say how
  * it is estimated).  Segments of seg_len samples every seg_len/2 samples,

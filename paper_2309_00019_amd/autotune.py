@@ -4,11 +4,13 @@ The two-pass filter stages a batch of templates' N-point intermediates between p
 pass B.  Small batches leave the GPU under-filled at the kernel boundaries; large ones push the
 intermediate out of the 256 MB Infinity Cache before pass B reads it back.  Pass B's tile (the
 rows of the intermediate one workgroup transforms) trades LDS per workgroup against the number
-of workgroups.  The best setting depends on N, the bank's band lengths and the candidate
-volume, so it is measured: the filter runs on a sample of the real bank and data for each
-candidate (device time from events on the library's stream), first over the batch budgets at
-the default tile, then over the tiles at the best budget, and the fastest is set on the context.
-Neither knob changes the results (same candidates, same values).
+of workgroups; pass A's tile (the columns one workgroup transforms) sets the width of the
+pieces in which each row of the intermediate is written.  The best setting depends on N, the
+bank's band lengths and the candidate volume, so it is measured: the filter runs on a sample of
+the real bank and data for each candidate (device time from events on the library's stream),
+first over the batch budgets at the default tiles, then over the pass-B tiles at the best budget,
+then over the pass-A tiles, and the fastest is set on the context.  No knob changes the results
+(same candidates, same values).
 """
 import torch
 
@@ -16,6 +18,7 @@ from . import hs
 
 BUDGETS_MB = (64, 96, 128, 160, 192, 256)
 TILES = (64, 128, 256)          # pass-B threads per workgroup
+PA_COLS = (16, 32, 64)          # pass-A columns per workgroup
 
 
 def _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps):
@@ -46,10 +49,12 @@ def tune_mf_batch(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, thr:
 
 
 def tune_mf_schedule(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, thr: float, budgets_mb=BUDGETS_MB,
-                     tiles=TILES, reps: int = 3):
-    """Batch budget, then pass-B tile; sets both on ctx and returns
-    {"batch_mb", "tile", "budgets": {mb: us/template}, "tiles": {threads: us/template}}."""
+                     tiles=TILES, pa_cols=PA_COLS, reps: int = 3):
+    """Batch budget, then pass-B tile, then pass-A tile; sets all three on ctx and returns
+    {"batch_mb", "tile", "pa_cols", "budgets": {mb: us/template}, "tiles": {threads: us/template},
+    "pa_tiles": {columns: us/template}}."""
     hs.hs_set_mf_tile(ctx, 128)
+    hs.hs_set_mf_pa_cols(ctx, 64)
     best_mb, budgets = tune_mf_batch(ctx, spec, n, fs, bank, tmpl_ids, thr, budgets_mb, reps)
     table = {}
     for t in tiles:
@@ -57,4 +62,11 @@ def tune_mf_schedule(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, t
         table[int(t)] = budgets[best_mb] if t == 128 else _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps)
     best_t = min(table, key=table.get)
     hs.hs_set_mf_tile(ctx, best_t)
-    return {"batch_mb": best_mb, "tile": best_t, "budgets": budgets, "tiles": table}
+    pa_table = {}
+    for c in pa_cols:
+        hs.hs_set_mf_pa_cols(ctx, int(c))
+        pa_table[int(c)] = table[best_t] if c == 64 else _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps)
+    best_c = min(pa_table, key=pa_table.get)
+    hs.hs_set_mf_pa_cols(ctx, best_c)
+    return {"batch_mb": best_mb, "tile": best_t, "pa_cols": best_c, "budgets": budgets, "tiles": table,
+            "pa_tiles": pa_table}

@@ -347,7 +347,7 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 5; }
+int hs_abi_version(void) { return 6; }
 
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
     HS_REQUIRE(ctx, "hs_set_mf_batch_bytes: null context");
@@ -368,6 +368,15 @@ int hs_set_mf_tile(hs_ctx *ctx, int32_t pass_b_threads) {
 }
 
 int32_t hs_get_mf_tile(const hs_ctx *ctx) { return ctx ? ctx->mf_pb_threads : 0; }
+
+int hs_set_mf_pa_cols(hs_ctx *ctx, int32_t cols) {
+    HS_REQUIRE(ctx, "hs_set_mf_pa_cols: null context");
+    HS_REQUIRE(cols == 16 || cols == 32 || cols == 64, "hs_set_mf_pa_cols: %d columns (16, 32 or 64)", (int)cols);
+    ctx->mf_pa_cols = cols;
+    return HS_OK;
+}
+
+int32_t hs_get_mf_pa_cols(const hs_ctx *ctx) { return ctx ? ctx->mf_pa_cols : 0; }
 
 int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     if (!ctx) return hs::set_error(HS_EINVAL, "hs_create: ctx is NULL");

@@ -67,6 +67,7 @@ struct hs_ctx {
     // Matched-filter batch budget for the pass-A/pass-B intermediate (bytes).
     size_t mf_batch_bytes = size_t(128) << 20;
     int mf_pb_threads = 128;  // matched-filter pass-B workgroup size (64, 128 or 256)
+    int mf_pa_cols = 64;      // matched-filter pass-A columns per workgroup (16, 32 or 64)
 };
 
 namespace hs {

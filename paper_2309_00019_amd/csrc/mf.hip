@@ -14,7 +14,7 @@
 // and a wavefront-ballot compaction: one atomic per wavefront that holds candidates.
 //
 // Pass A: a workgroup of 16 x COLS threads owns COLS consecutive columns k1 of one template
-// (COLS = 64, or 16 for N1 < 64); thread (c = tid % COLS, l = tid / COLS) loads x[l + 16 j],
+// (COLS = 16, 32 or 64, at most N1); thread (c = tid % COLS, l = tid / COLS) loads x[l + 16 j],
 // j < 16, of column c (COLS lanes read 8 COLS contiguous bytes of spectrum per row), does a
 // radix-16 DFT over j in registers, exchanges through LDS, and a second radix-16 DFT finishes
 // each 256-point transform; every row of the intermediate is written in pieces of 8 COLS bytes.
@@ -34,9 +34,10 @@
 
 namespace hs {
 
-// Pass-A columns per workgroup: 64 where N1 allows (each row of the intermediate is then written
-// in 512-byte pieces; 16 columns, i.e. 128-byte pieces, ran 4-5 % slower per template and 8
-// columns 43 %), else 16.  The exchange buffer holds 16 l-blocks of 16 x COLS values, padded.
+// Pass-A columns per workgroup (the context's pass-A tile, at most N1): each row of the
+// intermediate is written in pieces of 8 COLS bytes (at N = 2^19 64 columns, 512-byte pieces, ran
+// 4-5 % faster per template than 16 and 8 columns 43 % slower).  The exchange buffer holds 16
+// l-blocks of 16 x COLS values, padded.
 template <int COLS> constexpr int pa_lds_stride() { return COLS * 16 + COLS; }
 static constexpr int MF_STRIPES = 64;                 // candidate lists (power of two)
 
@@ -479,6 +480,7 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
 
     const int log2N = ilog2(n);
     const int N1 = (int)(n / 512);
+    const int pa_cols = ctx->mf_pa_cols < N1 ? ctx->mf_pa_cols : N1;  // 16, 32 or 64 (N1 >= 16)
     const size_t per_tmpl = (size_t)n * sizeof(float2);
     int64_t tb_max = (int64_t)(ctx->mf_batch_bytes / per_tmpl);
     if (tb_max < 1) tb_max = 1;
@@ -518,7 +520,8 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     for (int64_t id0 = 0; id0 < n_ids; id0 += tb_max) {
         const int32_t tb = (int32_t)((n_ids - id0) < tb_max ? (n_ids - id0) : tb_max);
         const float2 *d = static_cast<const float2 *>(spec);
-        if (N1 >= 64) HS_TRY((launch_pass_a<64>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
+        if (pa_cols == 64) HS_TRY((launch_pass_a<64>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
+        else if (pa_cols == 32) HS_TRY((launch_pass_a<32>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
         else HS_TRY((launch_pass_a<16>(ctx, bank, d, items, (int32_t)id0, tb, N1, tw512, twlo, twhi, Y)));
         HS_TRY(launch_pass_b<WRITE_Z>(ctx, N1, tb, Y, items, (int32_t)id0, thr2, twN1, sbuf, counter, stripe_cap,
                                       spill_cap, zout));

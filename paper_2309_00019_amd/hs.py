@@ -27,7 +27,8 @@ EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_wel
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
            "hs_chisq", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
            "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells", "hs_far_fit", "hs_far",
-           "hs_far_threshold", "hs_set_mf_batch_bytes", "hs_get_mf_batch_bytes", "hs_set_mf_tile", "hs_get_mf_tile"]
+           "hs_far_threshold", "hs_set_mf_batch_bytes", "hs_get_mf_batch_bytes", "hs_set_mf_tile", "hs_get_mf_tile",
+           "hs_set_mf_pa_cols", "hs_get_mf_pa_cols"]
 MLP_FEATURES, MLP_CELLS, MLP_PARAMS = 16, 64, 43456
 MLP_MODEL = 32 + MLP_PARAMS
 
@@ -85,12 +86,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_get_mf_batch_bytes": [P],
         "hs_set_mf_tile": [P, I32],
         "hs_get_mf_tile": [P],
+        "hs_set_mf_pa_cols": [P, I32],
+        "hs_get_mf_pa_cols": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = {"hs_last_error": ctypes.c_char_p, "hs_far_threshold": ctypes.c_double,
-                      "hs_get_mf_batch_bytes": ctypes.c_int64, "hs_get_mf_tile": ctypes.c_int32}.get(name, ctypes.c_int)
+                      "hs_get_mf_batch_bytes": ctypes.c_int64, "hs_get_mf_tile": ctypes.c_int32,
+                      "hs_get_mf_pa_cols": ctypes.c_int32}.get(name, ctypes.c_int)
     _lib = lib
     return lib
 
@@ -208,6 +212,14 @@ def hs_set_mf_tile(ctx: "Context", pass_b_threads: int):
 
 def hs_get_mf_tile(ctx: "Context") -> int:
     return int(_lib.hs_get_mf_tile(ctx.handle))
+
+
+def hs_set_mf_pa_cols(ctx: "Context", cols: int):
+    _check(_lib.hs_set_mf_pa_cols(ctx.handle, int(cols)), "hs_set_mf_pa_cols")
+
+
+def hs_get_mf_pa_cols(ctx: "Context") -> int:
+    return int(_lib.hs_get_mf_pa_cols(ctx.handle))
 
 
 def hs_abi_version() -> int:

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_abi_version_and_error_string_without_gpu():
     from paper_2309_00019_amd import hs
     lib = hs.load_library()
-    assert lib.hs_abi_version() == 5
+    assert lib.hs_abi_version() == 6
     assert isinstance(lib.hs_last_error(), bytes)
 
 
@@ -59,6 +59,7 @@ def test_argument_errors_need_no_gpu():
                                  None) == hs.HS_EINVAL
     assert lib.hs_set_mf_batch_bytes(None, 1 << 27) == hs.HS_EINVAL
     assert lib.hs_set_mf_tile(None, 128) == hs.HS_EINVAL and lib.hs_get_mf_tile(None) == 0
+    assert lib.hs_set_mf_pa_cols(None, 64) == hs.HS_EINVAL and lib.hs_get_mf_pa_cols(None) == 0
     assert lib.hs_get_mf_batch_bytes(None) == 0
 
 

@@ -610,8 +610,9 @@ def test_background_fit_and_far_end_to_end_on_identical_triggers(ctx):
 
 @pytest.mark.parametrize("n,fs", [(2 ** 13, 512.0), (2 ** 16, 2048.0), (2 ** 20, 2048.0)])
 def test_matched_filter_does_not_depend_on_the_schedule(ctx, n, fs):
-    """The autotuner's knobs (batch budget, pass-B tile) change only the schedule: candidates and
-    SNR series are identical for every setting (at 2^20 the 64-thread tile widens to one row)."""
+    """The autotuner's knobs (batch budget, pass-B tile, pass-A columns) change only the schedule:
+    candidates and SNR series are identical for every setting (at 2^20 the 64-thread tile widens
+    to one row; at 2^13, N1 = 16, every pass-A setting runs 16 columns)."""
     import torch
     from paper_2309_00019_amd import hs
     _say(f"schedule invariance n={n}")
@@ -622,10 +623,12 @@ def test_matched_filter_does_not_depend_on_the_schedule(ctx, n, fs):
     pb = device_bank(ctx, bank, psd_d, f_low)
     spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
     ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
-    old_b, old_t = hs.hs_get_mf_batch_bytes(ctx), hs.hs_get_mf_tile(ctx)
+    old_b, old_t, old_c = hs.hs_get_mf_batch_bytes(ctx), hs.hs_get_mf_tile(ctx), hs.hs_get_mf_pa_cols(ctx)
     out, zs = [], []
     try:
-        for tile in (64, 128, 256):
+        for cols, tile in ((64, 64), (64, 128), (64, 256), (32, 128), (16, 128)):
+            hs.hs_set_mf_pa_cols(ctx, cols)
+            assert hs.hs_get_mf_pa_cols(ctx) == cols
             hs.hs_set_mf_tile(ctx, tile)
             assert hs.hs_get_mf_tile(ctx) == tile
             # one template per launch (at least 1 MiB), three, all 37
@@ -638,6 +641,7 @@ def test_matched_filter_does_not_depend_on_the_schedule(ctx, n, fs):
     finally:
         hs.hs_set_mf_batch_bytes(ctx, old_b)
         hs.hs_set_mf_tile(ctx, old_t)
+        hs.hs_set_mf_pa_cols(ctx, old_c)
     assert len(out[0]) > (100 if n >= 2 ** 16 else 10)
     assert all(np.array_equal(out[0], o) for o in out[1:])
     assert all(np.array_equal(zs[0], z) for z in zs[1:])
@@ -645,3 +649,5 @@ def test_matched_filter_does_not_depend_on_the_schedule(ctx, n, fs):
         hs.hs_set_mf_batch_bytes(ctx, 1000)
     with pytest.raises(hs.HsError):
         hs.hs_set_mf_tile(ctx, 96)
+    with pytest.raises(hs.HsError):
+        hs.hs_set_mf_pa_cols(ctx, 8)
