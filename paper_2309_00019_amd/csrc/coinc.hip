@@ -50,10 +50,15 @@ __device__ __forceinline__ int64_t floor_div_r(int64_t a, int64_t b, double inv_
     return q;
 }
 
-// Calls f(k) for every slide k in [0, K] with |circ(d - k step)| <= window, d in [0, T).
+// Calls f(k) for every slide k in [0, K] with |circ(d - k step)| <= window, d in [0, T).  The
+// circular distance is |d + jw T - k step| for some integer jw; a jw whose interval
+// [d + jw T - window, d + jw T + window] misses [0, K step] admits no slide and is skipped before
+// any division (at most one jw remains when K step + 2 window < T).
 template <typename F>
 __device__ __forceinline__ void for_each_slide(int64_t d, const SlideGeom &g, F f) {
     for (int64_t jw = -1; jw <= g.jmax; ++jw) {
+        const int64_t e = d + jw * g.wrap;
+        if (e + g.window < 0 || e - g.window > g.K * g.step) continue;
         int64_t lo = -floor_div_r(g.window - d - jw * g.wrap, g.step, g.inv_step);  // ceil
         int64_t hi = floor_div_r(d + g.window + jw * g.wrap, g.step, g.inv_step);
         if (lo < 0) lo = 0;
