@@ -20,12 +20,13 @@
 // each 256-point transform; every row of the intermediate is written in pieces of 8 COLS bytes.
 // Pass B: each lane holds 16 points of a row; N1/16 lanes share a row; radix-16 passes with
 // LDS exchanges (Stockham indexing), the last pass ending in registers for the epilogue.
-// Both passes are bound by latency more than by bandwidth (a few workgroups per CU, LDS-limited),
-// so every global load of a workgroup is issued before its first LDS barrier: the band loads,
+// A few workgroups fit a CU (LDS-limited), so memory latency is hidden only if every global load
+// of a workgroup is issued before its first LDS barrier: the band loads,
 // one per-call record with the template's band and scale (instead of a chain ids -> offset ->
 // band), and in pass B one twiddle per radix group, whose powers are then formed by at most 14
 // products (relative error ~1e-6, far below the SNR tolerance) instead of table loads that would
-// wait behind each barrier.
+// wait behind each barrier.  So arranged, pass A streams at the HBM rate a device copy reaches
+// and pass B is bound by its VALU work.
 #include <cmath>
 
 #include "dft.h"
