@@ -215,7 +215,7 @@ template <> struct PassBPlan<2048> { static constexpr int R2 = 16, R3 = 8; };
 
 // Output index of register e after a pass with radix R at sub-transform size Ns.
 template <int LPR, int R, int Ns>
-__device__ __forceinline__ int pass_out_index(int ln, int e) {
+__host__ __device__ constexpr int pass_out_index(int ln, int e) {
     const int b = e / R, r = e % R;
     const int j = ln + LPR * b;
     return (j / Ns) * Ns * R + (j % Ns) + r * Ns;
@@ -228,16 +228,30 @@ __device__ __forceinline__ int pass_out_index(int ln, int e) {
 // elements use an XOR swizzle of the low five bits (no padding) and shorter rows one pad
 // element per 16; both were checked conflict-free for every pass of every plan with a model
 // of that bank mapping.
-template <int N1> __device__ __forceinline__ int lds_map(int i) {
+template <int N1> __host__ __device__ constexpr int lds_map(int i) {
     if constexpr (N1 >= 512) return i ^ (((i >> 5) ^ ((i >> 8) << 4)) & 31);
     else return i + (i >> 4);
 }
 template <int N1> constexpr int lds_row_len() { return N1 >= 512 ? N1 : N1 + N1 / 16; }
 
+// Every row index a pass touches is a lane part and a register part in disjoint bits (the lane
+// number below LPR, the register's offsets above it), and lds_map is linear in such a split: an
+// XOR map for rows of >= 512 elements, i + i/16 on disjoint bits otherwise.  So the byte address
+// is one per-lane value combined with a compile-time constant per register -- one XOR, or an
+// add that folds into the instruction's offset -- instead of the whole swizzle per access.
+template <int N1> __device__ __forceinline__ uint32_t lds_combine(uint32_t lane_b, uint32_t reg_b) {
+    if constexpr (N1 >= 512) return lane_b ^ reg_b;  // the row offset lies above the in-row bits
+    else return lane_b + reg_b;
+}
+
 template <int N1, int LPR, int R, int Ns>
-__device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int ln) {
+__device__ __forceinline__ void lds_write_pass(char *lds_b, uint32_t row_b, const float2 *v, int ln) {
+    const uint32_t lane_b = row_b + 8u * (uint32_t)lds_map<N1>(pass_out_index<LPR, R, Ns>(ln, 0));
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[lds_map<N1>(pass_out_index<LPR, R, Ns>(ln, e))] = v[e];
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t reg_b = 8u * (uint32_t)lds_map<N1>(pass_out_index<LPR, R, Ns>(0, e));
+        *reinterpret_cast<float2 *>(lds_b + lds_combine<N1>(lane_b, reg_b)) = v[e];
+    }
 }
 
 // Reads the inputs of a radix-R pass at sub-transform size Ns from LDS: butterfly j = ln + LPR b
@@ -245,14 +259,16 @@ __device__ __forceinline__ void lds_write_pass(float2 *row, const float2 *v, int
 // radix-R DFT.  The twiddles are the powers of one preloaded base per b, base[b] = W_N1^{k S},
 // formed by at most R - 2 products: no table load waits behind the LDS barrier.
 template <int N1, int LPR, int R, int Ns>
-__device__ __forceinline__ void lds_read_pass_pow(float2 *v, const float2 *row, int ln, const float2 *base) {
+__device__ __forceinline__ void lds_read_pass_pow(float2 *v, const char *lds_b, uint32_t row_b, int ln,
+                                                  const float2 *base) {
+    const uint32_t lane_b = row_b + 8u * (uint32_t)lds_map<N1>(ln);
 #pragma unroll
     for (int b = 0; b < 16 / R; ++b) {
-        const int j = ln + LPR * b;
         float2 w = base[b];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float2 x = row[lds_map<N1>(j + r * (N1 / R))];
+            const uint32_t reg_b = 8u * (uint32_t)lds_map<N1>(LPR * b + r * (N1 / R));
+            float2 x = *reinterpret_cast<const float2 *>(lds_b + lds_combine<N1>(lane_b, reg_b));
             if (r == 1) x = cmul(x, w);
             if (r > 1) {
                 w = cmul(w, base[b]);
@@ -301,17 +317,18 @@ __global__ __launch_bounds__(PBT) void mf_pass_b(const float2 *__restrict__ Y, c
     if constexpr (R2 > 1) pass_bases<N1, LPR, R2, 16>(base2, ln, twN1);
     if constexpr (R3 > 1) pass_bases<N1, LPR, R3, 16 * R2>(base3, ln, twN1);
     dft16<1>(v);
-    float2 *row = lds + (N1 > 16 ? lr * ROW : 0);
+    char *lds_b = reinterpret_cast<char *>(lds);
+    const uint32_t row_b = 8u * (uint32_t)(N1 > 16 ? lr * ROW : 0);
     if constexpr (R2 > 1) {
-        lds_write_pass<N1, LPR, 16, 1>(row, v, ln);
+        lds_write_pass<N1, LPR, 16, 1>(lds_b, row_b, v, ln);
         __syncthreads();
-        lds_read_pass_pow<N1, LPR, R2, 16>(v, row, ln, base2);
+        lds_read_pass_pow<N1, LPR, R2, 16>(v, lds_b, row_b, ln, base2);
     }
     if constexpr (R3 > 1) {
         __syncthreads();
-        lds_write_pass<N1, LPR, R2, 16>(row, v, ln);
+        lds_write_pass<N1, LPR, R2, 16>(lds_b, row_b, v, ln);
         __syncthreads();
-        lds_read_pass_pow<N1, LPR, R3, 16 * R2>(v, row, ln, base3);
+        lds_read_pass_pow<N1, LPR, R3, 16 * R2>(v, lds_b, row_b, ln, base3);
     }
     constexpr int RL = R3 > 1 ? R3 : (R2 > 1 ? R2 : 16);
     constexpr int NsL = R3 > 1 ? 16 * R2 : (R2 > 1 ? 16 : 1);
