@@ -110,8 +110,14 @@ def found_injections(coincs_rec, inj_ticks, tol_ticks, snr_c_min=8.0):
     return found
 
 
-def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2):
-    """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores)."""
+SNR_TOLERANCE = {"f32": 1e-4, "bf16": 4e-3, "f16": 1e-3}   # relative rho, per template storage
+
+
+def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None):
+    """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores).
+
+    With a context it also returns the SNR error of the GPU path against that FP64 filter on the
+    sample's first templates (same data and PSD on both sides): (baseline dict, error dict)."""
     import oracle
     L = int(4 * fs)
     psd = oracle.psd_on_grid(oracle.welch_psd(strain_h.astype(np.float64), fs, L), fs, L, n)
@@ -128,9 +134,35 @@ def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2):
         t_used += time.perf_counter() - t0
         done += len(take)
     T = n / fs
-    return {"value": done * T / t_used, "unit": "template-s/s", "cores": 1, "kind": "oracle",
+    base = {"value": done * T / t_used, "unit": "template-s/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} fine templates x 1 detector x {T:.0f} s at {fs:.0f} Hz: FP64 matched filter "
                       f"+ threshold (numpy FFT, one thread), {t_used:.1f} s"}
+    if ctx is None:
+        return base, None
+    import torch
+    from paper_2309_00019_amd import hs
+    take = order[:8]
+    b = synth.taylorf2_bank(m1[take], m2[take], n, fs, f_low)
+    ref = oracle.filter_bank(st, psd, n, fs, f_low, b, np.arange(len(take)), 4.0, keep_series=True)["series"]
+    dev = ctx.device
+    psd_d = torch.as_tensor(psd, device=dev)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(strain_h, device=dev), fs, f_low, psd_d)
+    pb = hs.hs_prepare_bank(ctx, n, fs, f_low, psd_d, torch.as_tensor(b.data, device=dev),
+                            torch.as_tensor(b.offset, device=dev), torch.as_tensor(b.k0, device=dev),
+                            torch.as_tensor(b.kstart, device=dev), torch.as_tensor(b.k1, device=dev), args.dtype)
+    z = hs.hs_snr_series(ctx, spec, n, fs, pb, torch.arange(len(take), dtype=torch.int32, device=dev)).cpu().numpy()
+    rel = []
+    for t in range(len(take)):
+        r = np.abs(ref[t])
+        sel = r >= 4.0
+        rel.append(np.abs(np.abs(z[t][sel]) / r[sel] - 1.0))
+    rel = np.concatenate(rel)
+    err = {"storage": args.dtype, "templates": int(len(take)), "samples_rho_ge_4": int(rel.size),
+           "max_rel": float(rel.max()) if rel.size else 0.0,
+           "rms_rel": float(np.sqrt(np.mean(rel ** 2))) if rel.size else 0.0,
+           "tolerance_rel": SNR_TOLERANCE[args.dtype],
+           "against": "the FP64 matched filter of the cpu_baseline sample (same strain and PSD)"}
+    return base, err
 
 
 def main():
@@ -410,7 +442,8 @@ def main():
         out["injections"] = inj_out
     if not args.no_cpu:
         log("[cpu] timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(args, synth, n, fs, f_low, strains[0], fm1, fm2)
+        out["cpu_baseline"], out["snr_error_vs_fp64"] = cpu_baseline(args, synth, n, fs, f_low, strains[0], fm1,
+                                                                     fm2, ctx)
     ctx.close()
     print(json.dumps(out), flush=True)
 
