@@ -559,14 +559,17 @@ def test_exact_capacity_holds_unevenly_spread_candidates(ctx):
 # ------------------------------------------------------------------------------------------
 # Background tail fit and hybrid FAR (Sec. IV, Eqs. (6)-(7))
 # ------------------------------------------------------------------------------------------
-def test_far_of_synthetic_records_matches_oracle(ctx):
+@pytest.mark.parametrize("n_rec,n_slides,sort", [(5000, 40, True), (20000, 2, False)])
+def test_far_of_synthetic_records_matches_oracle(ctx, n_rec, n_slides, sort):
+    """Sorted output of hs_timeslide_coinc, and an unsorted array where a third of the records
+    are zero-lag ones (several listed records per thread, many staged chunks)."""
     from paper_2309_00019_amd import hs
     from oracle import farfit as F
-    _say("far synthetic records")
+    _say(f"far synthetic records n={n_rec} slides={n_slides}")
     g = np.random.default_rng(710)
-    co = synth.synthetic_coincs(g, 5000, 30, 51200 * 256, 51200 * 256, 40, stat=(36.0, 140.0))
-    co = co[np.lexsort((co["tick_h"], co["slide"]))]
-    t_b = 40 * 256.0
+    co = synth.synthetic_coincs(g, n_rec, 30, 51200 * 256, 51200 * 256, n_slides, stat=(36.0, 140.0))
+    co = co[np.lexsort((co["tick_h"], co["slide"]))] if sort else co[g.permutation(len(co))]
+    t_b = n_slides * 256.0
     alpha, beta, x_fit = 15.0, -1.3, 10.5
     got = hs.hs_far(ctx, hs.to_device_records(co, ctx.device), t_b, alpha, beta, x_fit).cpu().numpy()
     fg = co["slide"] == 0
