@@ -194,6 +194,47 @@ def test_matched_filter_candidates_follow_tolerance_rule(ctx, n, fs, f_low, kind
     assert worst < DELTA["f32"]
 
 
+@pytest.mark.parametrize("tile", [128, 256])
+def test_matched_filter_in_the_benchmark_launch_shape(ctx, tile):
+    """The benchmark's launch configuration at its full size: N = 2^19 at 2048 Hz, templates of
+    its fine bank, 192 MB intermediates (48 templates per launch pair, here 50 templates: a full
+    launch and a ragged one of 2), 64-column pass A, 128- or 256-thread pass B.  Sampled
+    templates of both launches against the oracle, one by one."""
+    import torch
+    from paper_2309_00019_amd import hs, workload
+    _say(f"benchmark launch shape tile={tile}")
+    n, fs, f_low, thr = 2 ** 19, 2048.0, workload.F_LOW, 4.0
+    fm1, fm2 = workload.bank_masses(30000, 0)
+    pick = np.linspace(0, 29999, 50).astype(np.int64)
+    bank = synth.taylorf2_bank(fm1[pick], fm2[pick], n, fs, f_low)
+    s = _strain(17, 0, n, fs, f_low, glitch_rate=0.05)
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    ids = torch.arange(bank.n_tmpl, dtype=torch.int32, device=ctx.device)
+    old = hs.hs_get_mf_batch_bytes(ctx), hs.hs_get_mf_tile(ctx), hs.hs_get_mf_pa_cols(ctx)
+    try:
+        hs.hs_set_mf_batch_bytes(ctx, 192 << 20)
+        hs.hs_set_mf_tile(ctx, tile)
+        hs.hs_set_mf_pa_cols(ctx, 64)
+        assert hs.mf_batch_templates(n, bank.n_tmpl, ctx) == 48
+        cand = hs.as_records(hs.hs_matched_filter(ctx, spec, n, fs, pb, ids, thr), hs.CANDIDATE)
+    finally:
+        hs.hs_set_mf_batch_bytes(ctx, old[0])
+        hs.hs_set_mf_tile(ctx, old[1])
+        hs.hs_set_mf_pa_cols(ctx, old[2])
+    assert len(cand) > 1000
+    st = oracle.strain_fft(s, fs)
+    worst = 0.0
+    for t in (0, 13, 31, 47, 48, 49):   # first launch (start, middle, last) and the ragged one
+        a, b = oracle.band_edges(n, fs, f_low, bank.kstart[t], bank.k1[t])
+        ref = oracle.snr_series(st, bank.spectrum(t), psd, n, fs, a, b)
+        sel = cand["tpos"] == t
+        worst = max(worst, check_candidates(cand["m"][sel], cand["rho2"][sel], ref, thr, DELTA["f32"]))
+    assert worst < DELTA["f32"]
+
+
 @pytest.mark.parametrize("n,fs", [(2 ** 17, 512.0), (2 ** 20, 2048.0)])
 def test_snr_error_per_storage_precision(ctx, n, fs):
     """SNR error of FP32 / BF16 / FP16 template storage (FP32 transform and accumulation) against
