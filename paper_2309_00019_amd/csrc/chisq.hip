@@ -139,7 +139,9 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     __shared__ double2 ph[G][CQ_PH];
     __shared__ double2 red[CQ_THREADS / 64][G];
     const int64_t a0 = gfirst[blockIdx.x];
-    const int l = blockIdx.y;
+    // the last equal-power bin is the widest by far (up to ~80 % of a long template's band), so
+    // its workgroups are dispatched first and the short ones fill the end of the grid
+    const int l = p - 1 - (int)blockIdx.y;
     const int tid = threadIdx.x;
     const int t = trig[act[a0]].tmpl;
     int g = 1;
