@@ -2,7 +2,7 @@
 
 The two-pass filter stages a batch of templates' N-point intermediates between pass A and
 pass B.  Small batches leave the GPU under-filled at the kernel boundaries and pay each launch's
-ramp and tail more often; large ones leave a ragged last round of workgroups.  Pass B's tile (the
+ramp and tail more often; larger ones than the best have also measured slower.  Pass B's tile (the
 rows of the intermediate one workgroup transforms) trades LDS per workgroup against the number
 of workgroups; pass A's tile (the columns one workgroup transforms) sets the width of the
 pieces in which each row of the intermediate is written.  The best setting depends on N, the
