@@ -273,7 +273,8 @@ def test_snr_error_per_storage_precision(ctx, n, fs):
 # a4: clustering (identical candidate inputs -> exact)
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("seed,n,W", [(0, 8192, 512), (1, 2 ** 17, 512), (2, 2 ** 19, 2048), (3, 10000, 333),
-                                      (4, 5000, 8000), (5, 4096, 4096)])   # windows of n and more: one tile
+                                      (4, 5000, 8000), (5, 4096, 4096),    # windows of n and more: one tile
+                                      (6, 8192, 1)])                       # one sample per tile
 def test_cluster_exact_on_identical_inputs(ctx, seed, n, W):
     from paper_2309_00019_amd import hs
     import torch
