@@ -14,7 +14,8 @@
  *   hs_matched_filter   complex SNR series of Eq. (1)/(2), threshold (Sec. II)
  *   hs_snr_series       the same SNR series written out in full (diagnostics)
  *   hs_cluster_triggers peak clustering of above-threshold samples into triggers
- *   hs_chisq            power-consistency chi-square and re-weighted SNR (Eq. (4))
+ *   hs_chisq            power-consistency chi-square and re-weighted SNR (Eq. (4));
+ *                       hs_chisq_at_peaks for triggers carrying the filter's own z
  *   hs_timeslide_coinc  two-detector coincidence over time slides, per-slide
  *                       clustering, background counts for Eq. (6) (Secs. I-II)
  *   hs_followup         stage-1 selection and union of fine-bank neighbourhoods
@@ -243,6 +244,20 @@ int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, i
 int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
              const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
              float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out);
+
+/*
+ * hs_chisq for triggers at the filter's peaks: as hs_chisq, but every trigger
+ * with snr >= rho_min must carry the filter's own rho and arg z at its sample
+ * (snr and phase as hs_cluster_triggers writes them from hs_matched_filter's
+ * candidates for the same spec and bank).  The p bins partition the band over
+ * which the filter forms z, so sum_l z_l = z exactly; the widest bin's z_l is
+ * formed as z - sum of the other bins and its template elements are not read
+ * (for a long template that bin holds most of the band).  Results agree with
+ * hs_chisq to the filter's float32 error in z.  Same arguments and errors.
+ */
+int hs_chisq_at_peaks(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                      const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
+                      float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out);
 
 /*
  * Two-detector coincidence over time slides (Sec. I; Sec. II, Eq. (6)).

@@ -125,6 +125,20 @@ __device__ __forceinline__ void horner(const float2 *__restrict__ dspec, const t
 // last.  Every power of v used is an exact float64 sincospi of (E m mod N) / N, computed once per
 // workgroup (one per lane), so no twiddle table is read; v^256 is the same in every lane and
 // lives in scalar registers.
+// The widest of a template's p bins (the lowest index among equals).  The bins partition the
+// band over which the filter forms z, so sum_l z_l = z; for triggers that carry the filter's own
+// rho and arg z, the widest bin's sum is formed as z minus the others instead of being read.
+__device__ __forceinline__ int widest_bin(const int32_t *e, int p) {
+    int w = 0;
+    int32_t best = e[1] - e[0];
+    for (int l = 1; l < p; ++l)
+        if (e[l + 1] - e[l] > best) {
+            best = e[l + 1] - e[l];
+            w = l;
+        }
+    return w;
+}
+
 static constexpr int CQ_PH = 10;  // v^1, v^2, ..., v^128, v^256, v^b0
 
 template <typename ST>
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     const int64_t *__restrict__ offset, const int32_t *__restrict__ k0, const int32_t *__restrict__ klo,
     const int32_t *__restrict__ khi, const int32_t *__restrict__ edges, int p, const hs_trigger *trig,
     const uint32_t *__restrict__ act, int64_t n_act, const uint32_t *__restrict__ gfirst, int64_t seg_t0,
-    int64_t tps, double2 *__restrict__ zl) {
+    int64_t tps, bool skip_widest, double2 *__restrict__ zl) {
     static_assert(CQ_THREADS == 256, "the tree below joins four wavefronts of 64 with v^64 and v^128");
     constexpr int G = CQ_GROUP;
     __shared__ double2 ph[G][CQ_PH];
@@ -147,6 +161,7 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
     int g = 1;
     while (g < G && a0 + g < n_act && trig[act[a0 + g]].tmpl == t) ++g;
     const int32_t *e = edges + (int64_t)t * (p + 1);
+    if (skip_widest && l == widest_bin(e, p)) return;  // formed from the peak in chisq_finish
     const int64_t base = offset[t] - k0[t];
     // every bin is clamped to the template's band, which lies inside [1, n/2 - 1]
     const int64_t band_lo = klo[t] > 1 ? klo[t] : 1;
@@ -211,23 +226,39 @@ __global__ __launch_bounds__(CQ_THREADS) void chisq_bin_sums(
 }
 
 // chi2 = p sum_l |z_l - z/p|^2, chi2_r = chi2 / (2p - 2), Eq. (4) re-weighting; one thread per
-// active trigger.
+// active trigger.  With from_peak the trigger's rho and arg z give z, and the widest bin's z_l is
+// z minus the other bins' sums.
 __global__ void chisq_finish(const double2 *__restrict__ zl, const uint32_t *__restrict__ act, int64_t n_act, int p,
-                             const hs_trigger *trig, const float *__restrict__ r2s, float *__restrict__ chisq_out,
+                             const hs_trigger *trig, const float *__restrict__ r2s,
+                             const int32_t *__restrict__ edges, bool from_peak, float *__restrict__ chisq_out,
                              hs_trigger *trig_out, float *__restrict__ bins_out) {
     const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (a >= n_act) return;
     const uint32_t i = act[a];
     const hs_trigger tr = trig[i];
     const double s = sqrt((double)r2s[tr.tmpl]);  // undoes the storage scale of the template
+    const int w = from_peak ? widest_bin(edges + (int64_t)tr.tmpl * (p + 1), p) : -1;
     double Zr = 0.0, Zi = 0.0;
-    for (int l = 0; l < p; ++l) {
-        Zr += zl[a * p + l].x * s;
-        Zi += zl[a * p + l].y * s;
+    if (from_peak) {
+        Zr = (double)tr.snr * cos((double)tr.phase);
+        Zi = (double)tr.snr * sin((double)tr.phase);
+    } else {
+        for (int l = 0; l < p; ++l) {
+            Zr += zl[a * p + l].x * s;
+            Zi += zl[a * p + l].y * s;
+        }
     }
+    double wr = Zr, wi = Zi;  // the widest bin: z minus the others
+    if (from_peak)
+        for (int l = 0; l < p; ++l)
+            if (l != w) {
+                wr -= zl[a * p + l].x * s;
+                wi -= zl[a * p + l].y * s;
+            }
     double chi2 = 0.0;
     for (int l = 0; l < p; ++l) {
-        const double dr = zl[a * p + l].x * s - Zr / p, di = zl[a * p + l].y * s - Zi / p;
+        const double zr = l == w ? wr : zl[a * p + l].x * s, zi = l == w ? wi : zl[a * p + l].y * s;
+        const double dr = zr - Zr / p, di = zi - Zi / p;
         chi2 += dr * dr + di * di;
         if (bins_out) bins_out[(int64_t)i * p + l] = (float)(p * (dr * dr + di * di));
     }
@@ -243,10 +274,10 @@ __global__ void chisq_finish(const double2 *__restrict__ zl, const uint32_t *__r
 template <typename ST>
 static int launch_bin_sums(hs_ctx *ctx, dim3 gs, const float2 *d, int64_t n, const hs_bank *bank, int p,
                            const hs_trigger *trig, const uint32_t *act, int64_t n_act, const uint32_t *gfirst,
-                           int64_t seg_t0, int64_t tps, double2 *zl) {
+                           int64_t seg_t0, int64_t tps, bool skip_widest, double2 *zl) {
     hipLaunchKernelGGL(chisq_bin_sums<ST>, gs, dim3(CQ_THREADS), 0, ctx->stream, d, n,
                        static_cast<const typename ST::elem *>(bank->spectra), bank->offset, bank->k0, bank->k_lo,
-                       bank->k_hi, bank->chisq_edges, p, trig, act, n_act, gfirst, seg_t0, tps, zl);
+                       bank->k_hi, bank->chisq_edges, p, trig, act, n_act, gfirst, seg_t0, tps, skip_widest, zl);
     HS_HIP(hipGetLastError());
     return HS_OK;
 }
@@ -255,9 +286,9 @@ static int launch_bin_sums(hs_ctx *ctx, dim3 gs, const float2 *d, int64_t n, con
 
 using namespace hs;
 
-extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
-                        const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
-                        float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out) {
+static int chisq_impl(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                      const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
+                      float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out, bool from_peak) {
     HS_REQUIRE(ctx && bank, "hs_chisq: null argument");
     HS_REQUIRE(n_trig >= 0 && n_trig < (int64_t(1) << 31), "hs_chisq: bad trigger count");
     if (n_trig == 0) return HS_OK;
@@ -320,19 +351,34 @@ extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, con
     switch (bank->dtype) {
     case HS_F32:
         HS_TRY((launch_bin_sums<StoreF32>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
-                                          ticks_per_sample, zl)));
+                                          ticks_per_sample, from_peak, zl)));
         break;
     case HS_BF16:
         HS_TRY((launch_bin_sums<StoreBF16>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
-                                           ticks_per_sample, zl)));
+                                           ticks_per_sample, from_peak, zl)));
         break;
     default:
         HS_TRY((launch_bin_sums<StoreF16>(ctx, gs, d, n, bank, p, trig, act, (int64_t)n_act, gfirst, seg_t0,
-                                          ticks_per_sample, zl)));
+                                          ticks_per_sample, from_peak, zl)));
         break;
     }
     hipLaunchKernelGGL(chisq_finish, dim3((unsigned)cdiv((int64_t)n_act, 256)), dim3(256), 0, ctx->stream, zl, act,
-                       (int64_t)n_act, p, trig, bank->rho2_scale, chisq_out, trig_out, bins_out);
+                       (int64_t)n_act, p, trig, bank->rho2_scale, bank->chisq_edges, from_peak, chisq_out, trig_out,
+                       bins_out);
     HS_HIP(hipGetLastError());
     return HS_OK;
+}
+
+extern "C" int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                        const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
+                        float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out) {
+    return chisq_impl(ctx, spec, n, fs, bank, trig, n_trig, seg_t0, ticks_per_sample, rho_min, chisq_out, trig_out,
+                      bins_out, false);
+}
+
+extern "C" int hs_chisq_at_peaks(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                                 const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,
+                                 float rho_min, float *chisq_out, hs_trigger *trig_out, float *bins_out) {
+    return chisq_impl(ctx, spec, n, fs, bank, trig, n_trig, seg_t0, ticks_per_sample, rho_min, chisq_out, trig_out,
+                      bins_out, true);
 }

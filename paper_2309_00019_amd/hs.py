@@ -25,7 +25,7 @@ COINC = np.dtype([("slide", "<i4"), ("tmpl", "<i4"), ("tick_h", "<i8"), ("tick_l
                   ("snr_h", "<f4"), ("snr_l", "<f4"), ("stat", "<f4"), ("snr_c", "<f4")])
 EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_welch_psd", "hs_whiten",
            "hs_prepare_bank", "hs_matched_filter", "hs_snr_series", "hs_cluster_triggers",
-           "hs_chisq", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
+           "hs_chisq", "hs_chisq_at_peaks", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
            "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells", "hs_far_fit", "hs_far",
            "hs_far_threshold", "hs_set_mf_batch_bytes", "hs_get_mf_batch_bytes", "hs_set_mf_tile", "hs_get_mf_tile",
            "hs_set_mf_pa_cols", "hs_get_mf_pa_cols"]
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
         "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
         "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
+        "hs_chisq_at_peaks": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
         "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, P, I32, P, P, I64,
                                ctypes.POINTER(I64)],
         "hs_followup": [P, P, I64, F, P, I32, P, I32, D, I64, I32, P, P],
@@ -340,9 +341,10 @@ def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: 
 
 
 def hs_chisq(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, trig, seg_t0: int = 0,
-             ticks_per_sample: int = 1, rho_min: float = 0.0, out=None, bins: bool = False):
+             ticks_per_sample: int = 1, rho_min: float = 0.0, out=None, bins: bool = False, at_peaks: bool = False):
     """Returns (float32 [n_trig] chi2_r, int32 [n_trig, 6] triggers with snr re-weighted by Eq. (4))
-    and, with bins=True, a third item: float32 [n_trig, p] per-bin chi-square terms."""
+    and, with bins=True, a third item: float32 [n_trig, p] per-bin chi-square terms.
+    at_peaks=True calls hs_chisq_at_peaks (triggers must carry the filter's own rho and arg z)."""
     _dev(spec, torch.complex64, "spec")
     _dev(trig, torch.int32, "trig")
     n_trig = trig.shape[0]
@@ -350,8 +352,10 @@ def hs_chisq(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, trig, se
     out = torch.empty_like(trig) if out is None else out
     b = torch.empty((n_trig, max(1, bank.chisq_bins)), dtype=torch.float32, device=trig.device) if bins else None
     bs = bank.struct()
-    _check(_lib.hs_chisq(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(trig), n_trig, seg_t0,
-                         ticks_per_sample, float(rho_min), _ptr(chi), _ptr(out), _ptr(b)), "hs_chisq")
+    fn = _lib.hs_chisq_at_peaks if at_peaks else _lib.hs_chisq
+    _check(fn(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(trig), n_trig, seg_t0,
+              ticks_per_sample, float(rho_min), _ptr(chi), _ptr(out), _ptr(b)),
+           "hs_chisq_at_peaks" if at_peaks else "hs_chisq")
     return (chi, out, b) if bins else (chi, out)
 
 

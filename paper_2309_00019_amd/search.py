@@ -115,8 +115,9 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
         trig = hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks, ticks_per_sample=tps)
         if use_chisq:
             # Eq. (4): the coincidence statistic combines re-weighted SNRs
+            # the triggers carry the filter's own rho and arg z: the widest bin is formed from them
             r = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
-                            rho_min=cfg.chisq_rho_min, out=trig, bins=with_chisq)
+                            rho_min=cfg.chisq_rho_min, out=trig, bins=with_chisq, at_peaks=True)
             if with_chisq:
                 chis.append(r[0])
                 bins.append(r[2])

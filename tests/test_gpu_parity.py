@@ -485,12 +485,15 @@ def test_invalid_template_ids_are_rejected(ctx):
 # ------------------------------------------------------------------------------------------
 # Eq. (4): power-consistency chi-square and re-weighted SNR
 # ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("at_peaks", [False, True])
 @pytest.mark.parametrize("n,fs,f_low,kind", [(2 ** 13, 512.0, 30.0, "eq"), (2 ** 17, 512.0, 20.0, "tau"),
                                              (2 ** 19, 2048.0, 20.0, "tau")])
-def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind):
+def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind, at_peaks):
+    """hs_chisq, and hs_chisq_at_peaks on the filter's own triggers (the widest bin formed as z minus
+    the other bins), against the oracle's chi-square of its own triggers."""
     import torch
     from paper_2309_00019_amd import hs
-    _say(f"chisq n={n}")
+    _say(f"chisq n={n} at_peaks={at_peaks}")
     bank = _bank_for(kind, n, fs, f_low, count=6, seed=18)
     inj = dict(m1=bank.m1[1], m2=bank.m2[1], t_c=0.41 * n / fs, phi_c=0.2, snr=25.0)
     s = _strain(18, 0, n, fs, f_low, glitch_rate=0.2, injections=[inj])
@@ -509,10 +512,14 @@ def test_chisq_edges_and_reweighted_snr_match_oracle(ctx, n, fs, f_low, kind):
     trig = hs.hs_cluster_triggers(ctx, cand, n, ids, int(fs), seg_t0=t0, ticks_per_sample=tps)
     tr = hs.as_records(trig, hs.TRIGGER)
     assert len(tr) > 10 and tr["snr"].max() > 15
-    chi, rw, bins = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=5.0, bins=True)
+    chi, rw, bins = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=5.0, bins=True,
+                                at_peaks=at_peaks)
     chi, bins = chi.cpu().numpy(), bins.cpu().numpy()
     rw = hs.as_records(rw, hs.TRIGGER)
     assert np.array_equal(rw["tick"], tr["tick"]) and np.array_equal(rw["tmpl"], tr["tmpl"])
+    if at_peaks:   # the two entry points agree to the filter's float32 error in z
+        chi_full = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=5.0)[0]
+        assert np.allclose(chi, chi_full.cpu().numpy(), rtol=1e-4, atol=1e-4)
     # the oracle's own triggers (filter, cluster, chi-square at its own samples)
     ids_np = np.arange(bank.n_tmpl)
     c = oracle.filter_bank(st, psd, n, fs, f_low, bank, ids_np, 4.0)
