@@ -61,6 +61,22 @@ def test_chisq_vanishes_for_the_matching_signal_and_z_is_the_snr():
     assert chi2_r < 1e-3 * abs(z) ** 2 / 8
 
 
+def test_bin_snrs_sum_to_the_fft_snr_at_every_sample_in_noise():
+    # the p bins tile the filter's band, so the per-bin sums add up to z[m] of the inverse FFT at
+    # any sample, signal or not (the identity that lets the widest bin be formed from z)
+    n, fs, f_low = 8192, 512.0, 30.0
+    b, h, psd, k_lo, k_hi, sig = _setup(14.0, n, fs, f_low)
+    s, _ = synth.make_strain(911, 0, 3, n, fs, f_low)
+    st = oracle.strain_fft(s, fs)
+    zs = oracle.snr_series(st, h, psd, n, fs, k_lo, k_hi, sig)
+    for p in (2, 5, 8, 16):
+        e = oracle.chisq_bin_edges(h, psd, k_lo, k_hi, p)
+        for m in (0, 1, 777, n // 2, n - 1):
+            zl = oracle.bin_snrs(st, h, psd, n, fs, sig, m, e)
+            assert abs(zl.sum() - zs[m]) < 1e-9 * max(1.0, abs(zs[m]))
+            assert abs(oracle.chisq_at(st, h, psd, n, fs, sig, m, e)[1] - zs[m]) < 1e-9 * max(1.0, abs(zs[m]))
+
+
 def test_chisq_flags_a_loud_sine_gaussian():
     n, fs, f_low = 8192, 512.0, 30.0
     b, h, psd, k_lo, k_hi, sig = _setup(9.0, n, fs, f_low)
