@@ -268,3 +268,95 @@ def test_eq8_reproduces_printed_hanford_speedup():
     s3 = oracle.speedup_eq8(a["n_seg"], a["n_flat"], a["n_stage1"], a["n_stage2"], a["f_flat"],
                             a["f_coarse"], a["t_seg"], 3.0)
     assert abs(s3 - g["printed"]["speedup_gamma3"]) / g["printed"]["speedup_gamma3"] < 0.01
+
+
+# --------------------------------------------------------------------------------------
+# Band edge, whitened data and PSD interpolation: hand cases and direct sums
+# --------------------------------------------------------------------------------------
+def test_lowest_bin_hand_cases():
+    # df = 512 / 4096 = 0.125 Hz: 30.1 Hz sits between bins 240 (30.0 Hz) and 241 (30.125 Hz);
+    # the band starts at the first bin at or above f_low (a floor would give 240)
+    assert oracle.lowest_bin(4096, 512.0, 30.1) == 241
+    # f_low exactly on a bin: that bin is in the band
+    assert oracle.lowest_bin(4096, 512.0, 30.0) == 240
+    # just above a bin by one part in 1e12 of df still moves to the next bin
+    assert oracle.lowest_bin(4096, 512.0, 30.0 + 0.125e-9) == 241
+    # DC never enters the band
+    assert oracle.lowest_bin(4096, 512.0, 0.0) == 1
+    assert oracle.lowest_bin(4096, 512.0, 0.01) == 1
+    # a non-power-of-two length: df = 100 / 1000 = 0.1 Hz, 20.05 Hz -> bin 201
+    assert oracle.lowest_bin(1000, 100.0, 20.05) == 201
+
+
+@pytest.mark.parametrize("n,fs,f_low", [(256, 64.0, 7.3), (512, 100.0, 11.11), (1024, 512.0, 30.2)])
+def test_whitened_spectrum_is_direct_dft_over_sqrt_psd(n, fs, f_low):
+    # f_low * n / fs is not an integer in any case, so a floor for the ceiling shows
+    assert abs(f_low * n / fs - round(f_low * n / fs)) > 0.05
+    g = np.random.default_rng(int(n + fs))
+    s = g.standard_normal(n) * 2.0
+    psd = 0.3 + g.random(n // 2 + 1)
+    d = oracle.whitened_spectrum(s, fs, f_low, psd)
+    assert d.shape == (n // 2,)                      # bins 0 .. n/2 - 1: Nyquist is not stored
+    first = int(np.floor(f_low * n / fs)) + 1        # first bin with k df >= f_low
+    j = np.arange(n)
+    for k in range(n // 2):
+        if k < first:
+            assert d[k] == 0, k                      # DC and bins below f_low
+        else:
+            direct = np.sum(s * np.exp(-2j * np.pi * k * j / n)) / fs / np.sqrt(psd[k])
+            assert abs(d[k] - direct) <= 1e-12 * max(1.0, abs(direct)), k
+    assert d[first] != 0 and d[n // 2 - 1] != 0      # the band's first bin and the last stored bin
+
+
+def test_psd_on_grid_interpolates_linearly():
+    fs, L, n = 64.0, 16, 64
+    # a PSD linear in f is reproduced exactly on the finer grid
+    fw = np.arange(L // 2 + 1) * fs / L
+    lin = 2.0 + 0.25 * fw
+    out = oracle.psd_on_grid(lin, fs, L, n)
+    fk = np.arange(n // 2 + 1) * fs / n
+    assert out.shape == (n // 2 + 1,)
+    assert np.allclose(out, 2.0 + 0.25 * fk, rtol=0, atol=1e-13)
+    # hand case: the Welch grid has 4 Hz spacing, the segment grid 1 Hz; at 1/4, 1/2, 3/4 of
+    # the way between two Welch bins the value moves that fraction of the way
+    p = np.array([1.0, 5.0, 3.0, 3.0, 7.0, 1.0, 2.0, 2.0, 9.0])
+    out = oracle.psd_on_grid(p, fs, L, n)
+    assert out[0] == 1.0 and out[4] == 5.0 and out[8] == 3.0 and out[32] == 9.0
+    assert np.allclose(out[1:4], [2.0, 3.0, 4.0], rtol=0, atol=1e-15)
+    assert np.allclose(out[5:8], [4.5, 4.0, 3.5], rtol=0, atol=1e-15)
+    assert np.allclose(out[17:20], [5.5, 4.0, 2.5], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_timeslide_coinc_matches_bruteforce_over_many_wraps(seed):
+    # the slides go round the ring several times (K step = 1.5 .. 8 wraps), windows reach from a
+    # few ticks to beyond one step, so a pair is coincident at several slides of one wrap or of
+    # several wraps
+    g = np.random.default_rng(300 + seed)
+    wrap = int(g.choice([3000, 3001, 2999]))
+    step = int(g.integers(70, 401))
+    K = int(g.integers(20, 61))
+    window = int(g.choice([int(g.integers(3, 40)), int(g.integers(40, step // 2 + 1)),
+                           int(g.integers(step, min(1400, wrap // 2 - 1)))]))
+    cw = int(g.integers(20, 1000))
+    th = synth.synthetic_triggers(g, 3, wrap, 6, 7, wrap)
+    tl = synth.synthetic_triggers(g, 3, wrap, 6, 7, wrap)
+    tl["snr"][: len(tl) // 3] = th["snr"][0]
+    h = dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"])
+    l = dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"])
+    assert K * step >= 1.5 * wrap
+    edges = np.array([4.0, 6.0, 8.0, 11.0, 14.0], np.float32)
+    out = oracle.timeslide_coinc(h, l, K, step, window, wrap, cw, edges, 100)
+    pairs, kept, stat = _brute_coinc(h, l, K, step, window, wrap, cw)
+    c = out["coincs"]
+    got = sorted(zip(c["slide"].tolist(), c["tmpl"].tolist(), c["tick_h"].tolist(), c["tick_l"].tolist()))
+    exp = sorted((k, int(h["tmpl"][i]), int(h["tick"][i]), int(l["tick"][j])) for k, i, j in kept)
+    assert got == exp and len(exp) > 0
+    # a pair really coincides on more than one wrap of the ring in these cases
+    ks = {}
+    for k, i, j in pairs:
+        ks.setdefault((i, j), []).append(k * step // wrap)
+    assert any(len(set(v)) > 1 for v in ks.values())
+    bg = [stat[p] for p in kept if p[0] >= 1]
+    for e, cnt in zip(edges, out["bg_counts"]):
+        assert cnt == sum(1 for s in bg if np.float64(s) >= np.float64(e) ** 2)
