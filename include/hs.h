@@ -205,6 +205,33 @@ int hs_matched_filter(hs_ctx *ctx, const void *spec, int64_t n, double fs, const
                       const int32_t *tmpl_ids, int32_t n_ids, float thr, hs_candidate *cand,
                       int64_t cap, int64_t *n_cand);
 
+/*
+ * hs_matched_filter without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as
+ * hs_matched_filter (same kernels; its twiddle tables are computed on the
+ * device in float64 and rounded once, so an SNR may differ from
+ * hs_matched_filter's by an ulp-level amount).  Its scratch (the pass-A ->
+ * pass-B intermediate, candidate lists, counters, per-template records and
+ * twiddles) lives in a fixed device array of HS_MF_NOALLOC_SCRATCH_BYTES per
+ * GPU, held until the process ends and located by hs_create; the call makes
+ * no hipMalloc, hipFree or pinned-host allocation, and copies its counts
+ * straight into the caller's host memory.  Templates are filtered in batches
+ * that fit the array beside the candidate lists (2 cap + 64 records of 16 B),
+ * n_ids records of 32 B and 36 KB of twiddles; HS_EINVAL when these leave no
+ * room for one template's 8 n-byte intermediate (at n = 2^19 with 1,000
+ * templates cap may reach about 1.96 M), or when the context's device is
+ * beyond 63.
+ * Every allocation-free call on one GPU shares that GPU's array and leaves
+ * its contents behind (counters are cleared at the start of each call):
+ * calls that overlap on one GPU (other streams, threads or contexts) race and
+ * must be serialised by the caller.
+ */
+#define HS_MF_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int hs_matched_filter_noalloc(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
+                              const int32_t *tmpl_ids, int32_t n_ids, float thr, hs_candidate *cand,
+                              int64_t cap, int64_t *n_cand);
+
 /* The complex SNR series z[m] of hs_matched_filter written out in full:
  * z_out device complex64 [n_ids][n]. */
 int hs_snr_series(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,

@@ -347,7 +347,7 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 7; }
+int hs_abi_version(void) { return 8; }
 
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
     HS_REQUIRE(ctx, "hs_set_mf_batch_bytes: null context");
@@ -385,6 +385,7 @@ int hs_create(hs_ctx **ctx, int device, void *hip_stream) {
     HS_HIP(hipGetDeviceCount(&n_dev));
     HS_REQUIRE(device >= 0 && device < n_dev, "hs_create: device %d out of range (%d devices)", device, n_dev);
     HS_HIP(hipSetDevice(device));
+    HS_TRY(hs::mf_noalloc_setup(device));
     hs_ctx *c = new (std::nothrow) hs_ctx();
     if (!c) return hs::set_error(HS_ENOMEM, "hs_create: out of host memory");
     c->device = device;

@@ -72,6 +72,9 @@ struct hs_ctx {
 
 namespace hs {
 
+// Looks up the current device's copy of the allocation-free matched filter's fixed scratch
+// (once per device; called by hs_create with that device current).
+int mf_noalloc_setup(int device);
 // Ensure the arena holds at least `bytes`; synchronises the stream before growing.
 int arena_reserve(hs_ctx *ctx, size_t bytes);
 // Ensure the pinned host staging holds at least `bytes`.

@@ -28,6 +28,7 @@
 // wait behind each barrier.  So arranged, pass A streams at the HBM rate a device copy reaches
 // and pass B is bound by its VALU work.
 #include <cmath>
+#include <mutex>
 
 #include "dft.h"
 #include "hs_internal.h"
@@ -476,9 +477,70 @@ static int launch_pass_a(hs_ctx *ctx, const hs_bank *bank, const float2 *d, cons
     return HS_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Fixed scratch of hs_matched_filter_noalloc.  Each device holds its own copy of this array for
+// the life of the process; host code reaches it only through the address hipGetSymbolAddress
+// returns for that device (the array's name is a host-side stand-in, not a device address).
+// Every allocation-free call on a device shares it, so such calls on one device must not overlap.
+// ---------------------------------------------------------------------------------------------
+static constexpr size_t MF_NOALLOC_BYTES = size_t(64) << 20;
+static_assert(MF_NOALLOC_BYTES == (size_t)HS_MF_NOALLOC_SCRATCH_BYTES, "header and library disagree");
+static __device__ __align__(256) char scratch[MF_NOALLOC_BYTES];
+static constexpr int MF_MAX_DEVICES = 64;
+static char *g_scratch_dev[MF_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Looks up this device's copy of the fixed scratch, once per device; `device` must be current.
+int mf_noalloc_setup(int device) {
+    if (device < 0 || device >= MF_MAX_DEVICES) return HS_OK;  // the allocation-free call then reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return HS_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        return set_error(HS_EDEVICE, "fixed matched-filter scratch: hipGetSymbolAddress failed on device %d: %s",
+                         device, hipGetErrorString(e));
+    g_scratch_dev[device] = static_cast<char *>(p);
+    return HS_OK;
+}
+
+static char *noalloc_scratch(int device) {
+    if (device < 0 || device >= MF_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+// The four twiddle tables the passes read, written into the fixed scratch (the arena path takes
+// them from the context's tables): table t holds exp(+2 pi i j / 2^lg[t]) for j < count[t],
+// from a float64 sincospi of the exact dyadic argument 2 j / 2^lg, rounded once to float32.
+struct MfTwSpec {
+    int32_t off[4], count[4], lg[4];
+};
+
+__global__ __launch_bounds__(256) void mf_twiddle_fill(float2 *__restrict__ out, MfTwSpec sp) {
+    const int t = blockIdx.y;
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < sp.count[t]; j += gridDim.x * 256) {
+        double s, c;
+        sincospi(2.0 * (double)j / (double)(int64_t(1) << sp.lg[t]), &s, &c);
+        out[sp.off[t] + j] = float2{(float)c, (float)s};
+    }
+}
+
+// Carves 256-byte aligned pieces out of the fixed scratch, in order.
+struct FixedCarver {
+    char *base;
+    size_t used = 0;
+    template <typename T>
+    void add(T **p, size_t count) {
+        *p = reinterpret_cast<T *>(base + used);
+        used += (count * sizeof(T) + 255) & ~size_t(255);
+    }
+};
+
 template <bool WRITE_Z>
 static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank, const int32_t *ids,
-                  int32_t n_ids, float thr, hs_candidate *cand, int64_t cap, int64_t *n_cand, float2 *zout) {
+                  int32_t n_ids, float thr, hs_candidate *cand, int64_t cap, int64_t *n_cand, float2 *zout,
+                  char *fixed = nullptr) {
     HS_REQUIRE(ctx && spec && bank && (ids || n_ids == 0), "matched filter: null argument");
     HS_REQUIRE(is_pow2(n) && n >= 8192 && n <= (int64_t(1) << 20),
                "matched filter: n must be a power of two in [2^13, 2^20] (got %lld)", (long long)n);
@@ -505,28 +567,65 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     if (tb_max > 65535) tb_max = 65535;
     if (tb_max > n_ids) tb_max = n_ids;
 
-    const float2 *tw512, *twlo, *twhi, *twN1;
-    HS_TRY(twiddles_f32(ctx, 9, &tw512));
-    HS_TRY(twiddles_f32(ctx, log2N, &twlo));
-    HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
-    HS_TRY(twiddles_f32(ctx, ilog2(N1), &twN1));
-
     // Striped candidate lists: MF_STRIPES lists sharing the caller's capacity equally plus a spill
     // list as large as the whole capacity, so every distribution of up to `cap` candidates fits.
     const int64_t stripe_cap = WRITE_Z ? 0 : cap / MF_STRIPES;
     const int64_t spill_cap = WRITE_Z ? 0 : cap;
+    const float2 *tw512, *twlo, *twhi, *twN1;
     float2 *Y;
     unsigned long long *counter;
     hs_candidate *sbuf;
     int32_t *bad;
     MfItem *items;
-    Carver cv;
-    cv.add(&Y, (size_t)tb_max * n);
-    cv.add(&counter, MF_STRIPES + 1);
-    cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap + spill_cap + 1);
-    cv.add(&bad, 1);
-    cv.add(&items, (size_t)n_ids);
-    HS_TRY(cv.commit(ctx));
+    if (!fixed) {
+        HS_TRY(twiddles_f32(ctx, 9, &tw512));
+        HS_TRY(twiddles_f32(ctx, log2N, &twlo));
+        HS_TRY(twiddles_f32(ctx, log2N - 10, &twhi));
+        HS_TRY(twiddles_f32(ctx, ilog2(N1), &twN1));
+        Carver cv;
+        cv.add(&Y, (size_t)tb_max * n);
+        cv.add(&counter, MF_STRIPES + 1);
+        cv.add(&sbuf, (size_t)MF_STRIPES * stripe_cap + spill_cap + 1);
+        cv.add(&bad, 1);
+        cv.add(&items, (size_t)n_ids);
+        HS_TRY(cv.commit(ctx));
+    } else {
+        // pass A reads entries j < 1024 of the length-n table and all n/1024 of the coarse one
+        MfTwSpec sp;
+        const int cnt[4] = {512, 1024, (int)(n >> 10), N1}, lg[4] = {9, log2N, log2N - 10, ilog2(N1)};
+        int off = 0;
+        for (int t = 0; t < 4; ++t) {
+            sp.off[t] = off;
+            sp.count[t] = cnt[t];
+            sp.lg[t] = lg[t];
+            off += cnt[t];
+        }
+        HS_REQUIRE(cap <= (int64_t)(MF_NOALLOC_BYTES / sizeof(hs_candidate)) &&
+                       n_ids <= (int32_t)(MF_NOALLOC_BYTES / sizeof(MfItem)),
+                   "hs_matched_filter_noalloc: capacity %lld or %d templates exceed the fixed scratch (%zu bytes)",
+                   (long long)cap, (int)n_ids, MF_NOALLOC_BYTES);
+        FixedCarver fc{fixed};
+        float2 *tw;
+        fc.add(&tw, (size_t)off);
+        fc.add(&counter, MF_STRIPES + 1);
+        fc.add(&sbuf, (size_t)MF_STRIPES * stripe_cap + spill_cap + 1);
+        fc.add(&bad, 1);
+        fc.add(&items, (size_t)n_ids);
+        const size_t one = (per_tmpl + 255) & ~size_t(255);
+        HS_REQUIRE(fc.used + one <= MF_NOALLOC_BYTES,
+                   "hs_matched_filter_noalloc: n=%lld, %d templates and capacity %lld need %zu bytes of scratch "
+                   "(with one template's %zu-byte intermediate); the fixed scratch holds %zu",
+                   (long long)n, (int)n_ids, (long long)cap, fc.used + one, per_tmpl, MF_NOALLOC_BYTES);
+        const int64_t room = (int64_t)((MF_NOALLOC_BYTES - fc.used) / per_tmpl);
+        if (tb_max > room) tb_max = room;
+        fc.add(&Y, (size_t)tb_max * n);
+        hipLaunchKernelGGL(mf_twiddle_fill, dim3(4, 4), dim3(256), 0, ctx->stream, tw, sp);
+        HS_HIP(hipGetLastError());
+        tw512 = tw + sp.off[0];
+        twlo = tw + sp.off[1];
+        twhi = tw + sp.off[2];
+        twN1 = tw + sp.off[3];
+    }
     HS_TRY(fill_u64(ctx, reinterpret_cast<uint64_t *>(counter), MF_STRIPES + 1, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
     hipLaunchKernelGGL(mf_items, dim3((unsigned)cdiv(n_ids, 256)), dim3(256), 0, ctx->stream, ids, n_ids,
@@ -551,7 +650,13 @@ static int run_mf(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
     }
     unsigned long long hc[MF_STRIPES + 1];
     int32_t hbad = 0;
-    HS_TRY(read_back2(ctx, counter, hc, sizeof(hc), bad, &hbad, sizeof(hbad)));
+    if (!fixed) {
+        HS_TRY(read_back2(ctx, counter, hc, sizeof(hc), bad, &hbad, sizeof(hbad)));
+    } else {  // no pinned staging (it is allocated on first use): copy straight to the host values
+        HS_HIP(hipMemcpyAsync(hc, counter, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream));
+        HS_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream));
+        HS_HIP(hipStreamSynchronize(ctx->stream));
+    }
     HS_REQUIRE(hbad == 0, "matched filter: template id out of range or bank band outside [1, n/2-1] (code %d)",
                hbad);
     if (!WRITE_Z) {
@@ -573,6 +678,16 @@ extern "C" int hs_matched_filter(hs_ctx *ctx, const void *spec, int64_t n, doubl
                                  const int32_t *tmpl_ids, int32_t n_ids, float thr, hs_candidate *cand, int64_t cap,
                                  int64_t *n_cand) {
     return run_mf<false>(ctx, spec, n, fs, bank, tmpl_ids, n_ids, thr, cand, cap, n_cand, nullptr);
+}
+
+extern "C" int hs_matched_filter_noalloc(hs_ctx *ctx, const void *spec, int64_t n, double fs,
+                                         const hs_bank *bank, const int32_t *tmpl_ids, int32_t n_ids, float thr,
+                                         hs_candidate *cand, int64_t cap, int64_t *n_cand) {
+    HS_REQUIRE(ctx, "hs_matched_filter_noalloc: null context");
+    char *fixed = noalloc_scratch(ctx->device);
+    HS_REQUIRE(fixed, "hs_matched_filter_noalloc: no fixed scratch on device %d (set up by hs_create; "
+               "devices 0..%d)", ctx->device, MF_MAX_DEVICES - 1);
+    return run_mf<false>(ctx, spec, n, fs, bank, tmpl_ids, n_ids, thr, cand, cap, n_cand, nullptr, fixed);
 }
 
 extern "C" int hs_snr_series(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,

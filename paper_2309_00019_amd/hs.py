@@ -28,7 +28,7 @@ EXPORTS = ["hs_create", "hs_destroy", "hs_last_error", "hs_abi_version", "hs_wel
            "hs_chisq", "hs_chisq_at_peaks", "hs_timeslide_coinc", "hs_followup", "hs_proposer_features", "hs_mlp_forward",
            "hs_mlp_train_step", "hs_mlp_propose", "hs_followup_cells", "hs_far_fit", "hs_far",
            "hs_far_threshold", "hs_set_mf_batch_bytes", "hs_get_mf_batch_bytes", "hs_set_mf_tile", "hs_get_mf_tile",
-           "hs_set_mf_pa_cols", "hs_get_mf_pa_cols"]
+           "hs_set_mf_pa_cols", "hs_get_mf_pa_cols", "hs_matched_filter_noalloc"]
 MLP_FEATURES, MLP_CELLS, MLP_PARAMS = 16, 64, 43456
 MLP_MODEL = 32 + MLP_PARAMS
 
@@ -68,6 +68,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_whiten": [P, P, I64, D, D, P, P],
         "hs_prepare_bank": [P, I64, D, D, P, I32, P, P, P, P, P, I32, P, P, P, P, P, I32, P],
         "hs_matched_filter": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
+        "hs_matched_filter_noalloc": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
         "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
         "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
         "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
@@ -306,6 +307,30 @@ def hs_matched_filter(ctx: Context, spec, n: int, fs: float, bank: PreparedBank,
         _check(st, "hs_matched_filter")
         return cand[: cnt.value]
     raise HsError(HS_EOVERFLOW, "hs_matched_filter: overflow after resize")
+
+
+MF_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def hs_matched_filter_noalloc(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, tmpl_ids, thr: float, cand):
+    """hs_matched_filter into a caller-allocated candidate buffer (device int32 [cap, 4]) through the
+    allocation-free entry point; returns the candidate count.  A count above cap raises HsError
+    (HS_EOVERFLOW) with the required count in ``HsError.required``."""
+    _dev(spec, torch.complex64, "spec")
+    _dev(tmpl_ids, torch.int32, "tmpl_ids")
+    _dev(cand, torch.int32, "cand")
+    if cand.dim() != 2 or cand.shape[1] != 4:
+        raise ValueError("cand must be an int32 [cap, 4] tensor of hs_candidate records")
+    bs = bank.struct()
+    cnt = ctypes.c_int64(0)
+    st = _lib.hs_matched_filter_noalloc(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(tmpl_ids),
+                                        tmpl_ids.numel(), float(thr), _ptr(cand), cand.shape[0], ctypes.byref(cnt))
+    if st == HS_EOVERFLOW:
+        err = HsError(st, "hs_matched_filter_noalloc: " + _lib.hs_last_error().decode(errors="replace"))
+        err.required = int(cnt.value)
+        raise err
+    _check(st, "hs_matched_filter_noalloc")
+    return int(cnt.value)
 
 
 def hs_snr_series(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, tmpl_ids, out=None):
