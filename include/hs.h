@@ -281,6 +281,9 @@ int hs_chisq(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank 
  * formed as z - sum of the other bins and its template elements are not read
  * (for a long template that bin holds most of the band).  Results agree with
  * hs_chisq to the filter's float32 error in z.  Same arguments and errors.
+ * The input must be the filter's own (unweighted) triggers: when trig_out
+ * aliases trig the buffer afterwards holds re-weighted SNRs, and passing it
+ * to hs_chisq_at_peaks again would take those for |z| (nothing detects this).
  */
 int hs_chisq_at_peaks(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_bank *bank,
                       const hs_trigger *trig, int64_t n_trig, int64_t seg_t0, int64_t ticks_per_sample,

@@ -5,7 +5,7 @@ multiples of a fixed step and recomputing coincidences; Eq. (6) gives
 FAR = (1 + n_b(Lambda_b >= Lambda*_f)) / T_b.  Readings taken where the paper
 is silent:
 
-* Coincidence (Sec. I: "coincident in time and the template parameters"):
+* Coincidence (Sec. I asks for agreement in time and in template parameters):
   same template id, and circular |delta| <= window with
   delta = ((t_H - t_L - k step + T/2) mod T) - T/2 on the integer tick grid,
   T = wrap (the analysed time on the concatenated timeline).  Slide k = 0 is the

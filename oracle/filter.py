@@ -14,8 +14,8 @@ min(last template bin, N/2 - 1) (f_high = the template's ISCO cut or Nyquist;
 DC and Nyquist excluded).  The time index m is the coalescence sample on the
 circular segment (t_c = m / fs).
 
-Threshold (Sec. II, "greater than or equal to"): rho >= thr, compared as
-rho^2 >= thr^2.  Peak clustering (Sec. II speaks of the "peak" of the SNR; the
+Threshold (Sec. II: inclusive): rho >= thr, compared as rho^2 >= thr^2.
+Peak clustering (Sec. II keeps the maximum of the SNR series as the trigger; the
 rule is not given): a candidate m is a trigger iff every other candidate m'
 with |m' - m| <= W has rho^2[m'] < rho^2[m], or rho^2[m'] == rho^2[m] and
 m' > m (ties go to the earlier sample); distance is linear within a segment.

@@ -57,16 +57,29 @@ __global__ void chisq_compact(const uint32_t *__restrict__ flag, const uint64_t 
 static constexpr int CQ_GROUP = 8;
 static constexpr int CQ_UNROLL = 2;
 
-__global__ void chisq_group_starts(const hs_trigger *trig, const uint32_t *__restrict__ act, int64_t n_act,
-                                   uint32_t *__restrict__ start) {
+// A new group starts at the first trigger of each run of one template and every CQ_GROUP
+// triggers within the run.  O(n_act): run starts are flagged, numbered by a prefix sum, and each
+// trigger's offset in its run is taken from its run's first index.
+__global__ void chisq_run_starts(const hs_trigger *trig, const uint32_t *__restrict__ act, int64_t n_act,
+                                 uint32_t *__restrict__ rs) {
     const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (a >= n_act) return;
-    // a new group at the start of each run of one template and every CQ_GROUP triggers within it
-    // (a run is at most one segment's triggers of a template: the backward walk is short)
-    const int32_t t = trig[act[a]].tmpl;
-    int64_t r = a;
-    while (r > 0 && trig[act[r - 1]].tmpl == t) --r;
-    start[a] = ((a - r) % CQ_GROUP == 0) ? 1u : 0u;
+    rs[a] = (a == 0 || trig[act[a - 1]].tmpl != trig[act[a]].tmpl) ? 1u : 0u;
+}
+
+__global__ void chisq_run_first(const uint32_t *__restrict__ rs, const uint64_t *__restrict__ roff, int64_t n_act,
+                                uint32_t *__restrict__ rfirst) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a < n_act && rs[a]) rfirst[roff[a]] = (uint32_t)a;
+}
+
+// In place: start[a] (holding the run-start flag on entry) becomes the group-start flag.
+__global__ void chisq_group_starts(const uint64_t *__restrict__ roff, const uint32_t *__restrict__ rfirst,
+                                   int64_t n_act, uint32_t *__restrict__ start) {
+    const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n_act) return;
+    const uint64_t run = roff[a] + start[a] - 1;  // inclusive count of run starts, minus one
+    start[a] = ((a - (int64_t)rfirst[run]) % CQ_GROUP == 0) ? 1u : 0u;
 }
 
 __global__ void chisq_group_list(const uint32_t *__restrict__ start, const uint64_t *__restrict__ off, int64_t n_act,
@@ -325,7 +338,7 @@ static int chisq_impl(hs_ctx *ctx, const void *spec, int64_t n, double fs, const
     HS_REQUIRE(hbad == 0, "hs_chisq: trigger template outside the bank or tick outside this segment (code %d)", hbad);
     if (n_act == 0) return HS_OK;
     double2 *zl;
-    uint32_t *gstart, *gfirst;
+    uint32_t *gstart, *gfirst, *rfirst;
     uint64_t *goff;
     Carver cv2;  // re-carves the same buffers first, then the groups and the bin sums
     cv2.add(&flag, n_trig);
@@ -337,9 +350,16 @@ static int chisq_impl(hs_ctx *ctx, const void *spec, int64_t n, double fs, const
     cv2.add(&gstart, (size_t)n_act);
     cv2.add(&goff, (size_t)n_act + 1);
     cv2.add(&gfirst, (size_t)n_act);
+    cv2.add(&rfirst, (size_t)n_act);
     HS_TRY(cv2.commit(ctx));
     const unsigned ga = (unsigned)cdiv((int64_t)n_act, 256);
-    hipLaunchKernelGGL(chisq_group_starts, dim3(ga), dim3(256), 0, ctx->stream, trig, act, (int64_t)n_act, gstart);
+    hipLaunchKernelGGL(chisq_run_starts, dim3(ga), dim3(256), 0, ctx->stream, trig, act, (int64_t)n_act, gstart);
+    HS_HIP(hipGetLastError());
+    HS_TRY(exclusive_scan_u32(ctx, gstart, (int64_t)n_act, goff, tmp));
+    hipLaunchKernelGGL(chisq_run_first, dim3(ga), dim3(256), 0, ctx->stream, gstart, goff, (int64_t)n_act, rfirst);
+    HS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(chisq_group_starts, dim3(ga), dim3(256), 0, ctx->stream, goff, rfirst, (int64_t)n_act,
+                       gstart);
     HS_HIP(hipGetLastError());
     HS_TRY(exclusive_scan_u32(ctx, gstart, (int64_t)n_act, goff, tmp));
     hipLaunchKernelGGL(chisq_group_list, dim3(ga), dim3(256), 0, ctx->stream, gstart, goff, (int64_t)n_act, gfirst);

@@ -1,7 +1,7 @@
 // Matched filter (Sec. II, Eqs. (1)-(2); quadrature form of Appendix A): for every template,
 //   z[m] = sum_{k in band} d~[k] conj(w~[k]) exp(+2 pi i k m / N),   m = 0..N-1,
 // with d~ the whitened data and w~ the prepared (whitened, sigma-normalised) template, then
-// rho^2 = |z|^2 compared against thr^2 (Sec. II: "greater than or equal to").
+// rho^2 = |z|^2 compared against thr^2 (Sec. II: the threshold is inclusive, rho >= thr).
 //
 // The N-point inverse transform is split four-step with N = 512 * N1:
 //   k = k1 + N1 k2  (k1 < N1, k2 < 512),   m = m2 + 512 m1  (m2 < 512, m1 < N1)

@@ -59,12 +59,15 @@ class SearchResult:
     template_seconds: float              # full-rate template-seconds filtered
     stage1_template_seconds: float = 0.0
     stage1_coincs: torch.Tensor = None
+    stage1_trig: tuple = None                       # (H, L) stage-1 triggers, re-weighted
     followed: list = field(default_factory=list)
     mf_ms: float = 0.0                   # device time inside matched-filter calls (events)
     mf_calls: int = 0
     mf_units: list = field(default_factory=list)   # (n, ids, bank) per matched-filter call
     far: dict = None                                # background_far() output, when computed
     fine_ids: list = None                           # per segment: followed fine template ids (device)
+    raw: dict = None                                # the filter's own triggers before re-weighting:
+                                                    # keys "h", "l" (full rate), "h1", "l1" (stage 1)
 
 
 class _MFTimer:
@@ -97,13 +100,17 @@ def whiten_all(ctx, strains, psds, cfg: SearchConfig):
     return out
 
 
-def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None, with_chisq=False):
+def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None, with_chisq=False,
+                      raw_sink=None):
     """Filter + cluster every segment of one detector; returns concatenated trigger records, and
-    with ``with_chisq`` also the chi2_r values and per-bin chi-square terms of those triggers."""
+    with ``with_chisq`` also the chi2_r values and per-bin chi-square terms of those triggers.
+    The chi-square writes the re-weighted triggers to a new buffer: the filter's own triggers
+    (rho and arg z at the peak, what hs_chisq_at_peaks needs) stay intact and, with a list as
+    ``raw_sink``, are appended to it (concatenated over segments)."""
     tps = int(round(cfg.ticks_per_second / fs))
     seg_ticks = specs.shape[1] * 2 * int(round(cfg.ticks_per_second / cfg.fs))
     window = int(round(cfg.window_sec * fs))
-    parts, chis, bins = [], [], []
+    parts, chis, bins, raws = [], [], [], []
     p = max(1, bank.chisq_bins)
     use_chisq = cfg.chisq_rho_min is not None and bank.chisq_bins
     for s in range(specs.shape[0]):
@@ -117,16 +124,22 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
             # Eq. (4): the coincidence statistic combines re-weighted SNRs
             # the triggers carry the filter's own rho and arg z: the widest bin is formed from them
             r = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
-                            rho_min=cfg.chisq_rho_min, out=trig, bins=with_chisq, at_peaks=True)
+                            rho_min=cfg.chisq_rho_min, bins=with_chisq, at_peaks=True)
+            raws.append(trig)
+            trig = r[1]
             if with_chisq:
                 chis.append(r[0])
                 bins.append(r[2])
-        elif with_chisq:
-            chis.append(torch.zeros(trig.shape[0], dtype=torch.float32, device=specs.device))
-            bins.append(torch.zeros((trig.shape[0], p), dtype=torch.float32, device=specs.device))
+        else:
+            raws.append(trig)
+            if with_chisq:
+                chis.append(torch.zeros(trig.shape[0], dtype=torch.float32, device=specs.device))
+                bins.append(torch.zeros((trig.shape[0], p), dtype=torch.float32, device=specs.device))
         parts.append(trig)
     cat = lambda xs, shape: torch.cat(xs) if xs else torch.zeros(shape, dtype=torch.float32, device=specs.device)
     trig = torch.cat(parts) if parts else torch.zeros((0, 6), dtype=torch.int32, device=specs.device)
+    if raw_sink is not None:
+        raw_sink.append(torch.cat(raws) if raws else torch.zeros((0, 6), dtype=torch.int32, device=specs.device))
     if not with_chisq:
         return trig
     return trig, cat(chis, (0,)), cat(bins, (0, p))
@@ -175,17 +188,18 @@ def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=
     fine = fine_h
     all_ids = torch.arange(fine.n_tmpl, dtype=torch.int32, device=spec_h.device)
     timer = _MFTimer(ctx, time_mf)
-    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, [all_ids] * n_seg, cfg.thr2, cfg, timer)
-    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, [all_ids] * n_seg, cfg.thr2, cfg, timer)
+    rh, rl = [], []
+    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rh)
+    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rl)
     wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
     co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
     T = n / cfg.fs
     apps = 2 * n_seg * fine.n_tmpl
     return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
-                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units)
+                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units, raw=dict(h=rh[0], l=rl[0]))
 
 
-def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=None, with_chisq=False):
+def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=None, with_chisq=False, raw=None):
     """Stage 1 of Sec. III: the coarse bank on the leading quarter of each whitened spectrum
     (ideal decimation to fs / decim, same df), threshold thr1, coincidence over zero lag and
     n_sh1 slides of t_sh1.  Returns (trig_h, trig_l, coincs) where with ``with_chisq`` each
@@ -194,8 +208,11 @@ def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=Non
     n1, fs1 = n // cfg.decim, cfg.fs / cfg.decim
     n_seg = spec_h.shape[0]
     c_ids = torch.arange(coarse_h.n_tmpl, dtype=torch.int32, device=spec_h.device)
-    th = detector_triggers(ctx, spec_h, n1, fs1, coarse_h, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq)
-    tl = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq)
+    rh, rl = [], []
+    th = detector_triggers(ctx, spec_h, n1, fs1, coarse_h, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq, rh)
+    tl = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq, rl)
+    if raw is not None:
+        raw.update(h1=rh[0], l1=rl[0])
     wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
     c1, _ = _coinc(ctx, th[0] if with_chisq else th, tl[0] if with_chisq else tl, coarse_h.n_tmpl, cfg.n_sh1,
                    cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32))
@@ -224,7 +241,8 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     seg_ticks = n * tpt
     wrap = n_seg * seg_ticks
     use_p = proposer is not None
-    t1h, t1l, c1 = stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg, timer, with_chisq=use_p)
+    raw = {}
+    t1h, t1l, c1 = stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg, timer, with_chisq=use_p, raw=raw)
     if use_p:
         # two tiers: rho_c >= rho1 keeps the cells of probability p_cum, rho_low <= rho_c < rho1
         # (marginal stage-1 coincidences, followed only through the proposer) those of p_cum_low
@@ -235,11 +253,14 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     else:
         ids2, counts = hs.hs_followup(ctx, c1, cfg.rho1, coarse.mchirp, fine.mchirp, cfg.mc_frac, seg_ticks, n_seg)
     per_seg = [ids2[s, :counts[s]] for s in range(n_seg)]
-    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, per_seg, cfg.thr2, cfg, timer)
-    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, per_seg, cfg.thr2, cfg, timer)
+    rh, rl = [], []
+    th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, per_seg, cfg.thr2, cfg, timer, raw_sink=rh)
+    tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, per_seg, cfg.thr2, cfg, timer, raw_sink=rl)
+    raw.update(h=rh[0], l=rl[0])
     co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
     T = n / cfg.fs
     apps = 2 * int(sum(counts))
     return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
                         stage1_template_seconds=2 * n_seg * coarse.n_tmpl * T, stage1_coincs=c1, followed=counts,
-                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units, fine_ids=per_seg)
+                        stage1_trig=(t1h[0] if use_p else t1h, t1l[0] if use_p else t1l),
+                        mf_ms=timer.ms, mf_calls=timer.calls, mf_units=timer.units, fine_ids=per_seg, raw=raw)
