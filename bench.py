@@ -113,30 +113,72 @@ def found_injections(coincs_rec, inj_ticks, tol_ticks, snr_c_min=8.0):
 SNR_TOLERANCE = {"f32": 1e-4, "bf16": 4e-3, "f16": 1e-3}   # relative rho, per template storage
 
 
+def _oracle_filter_share(job):
+    """One worker of the all-cores baseline: the oracle's filter over 8-template chunks of its
+    share of the sample until the time budget is spent; returns (templates, seconds)."""
+    import oracle
+    import synth
+    st, psd, n, fs, f_low, m1, m2, budget = job
+    done, t_used, k = 0, 0.0, 0
+    while t_used < budget and k < len(m1):
+        b = synth.taylorf2_bank(m1[k:k + 8], m2[k:k + 8], n, fs, f_low)
+        t0 = time.perf_counter()
+        oracle.filter_bank(st, psd, n, fs, f_low, b, np.arange(b.n_tmpl), 4.0)
+        t_used += time.perf_counter() - t0
+        done += b.n_tmpl
+        k += 8
+    return done, t_used
+
+
+def host_description():
+    """CPU model and counts of the host (from /proc/cpuinfo and the scheduler)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None):
-    """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores).
+    """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores):
+    one core in this process, then every usable core (at most 16, the machine's CPU share) as a
+    pool of spawned processes each running the unchanged oracle on its share of the templates.
 
     With a context it also returns the SNR error of the GPU path against that FP64 filter on the
     sample's first templates (same data and PSD on both sides): (baseline dict, error dict)."""
+    import multiprocessing as mp
     import oracle
     L = int(4 * fs)
     psd = oracle.psd_on_grid(oracle.welch_psd(strain_h.astype(np.float64), fs, L), fs, L, n)
     st = oracle.strain_fft(strain_h, fs)
     g = np.random.default_rng(5)
     order = g.permutation(len(m1))
-    done, t_used, k = 0, 0.0, 0
-    while t_used < args.cpu_seconds and k < len(order):
-        take = order[k:k + 8]
-        k += len(take)
-        b = synth.taylorf2_bank(m1[take], m2[take], n, fs, f_low)
-        t0 = time.perf_counter()
-        oracle.filter_bank(st, psd, n, fs, f_low, b, np.arange(len(take)), 4.0)
-        t_used += time.perf_counter() - t0
-        done += len(take)
+    done, t_used = _oracle_filter_share((st, psd, n, fs, f_low, m1[order], m2[order], args.cpu_seconds))
     T = n / fs
+    host = host_description()
+    workers = max(1, min(16, host["usable_cpus"] or 1))
+    rest = order[done:]
+    shares = [rest[w::workers] for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        got = pool.map(_oracle_filter_share, [(st, psd, n, fs, f_low, m1[sh], m2[sh], args.cpu_seconds)
+                                              for sh in shares])
+    wall = time.perf_counter() - t0
+    done_all = sum(d for d, _ in got)
+    busy = max(t for _, t in got)
     base = {"value": done * T / t_used, "unit": "template-s/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} fine templates x 1 detector x {T:.0f} s at {fs:.0f} Hz: FP64 matched filter "
-                      f"+ threshold (numpy FFT, one thread), {t_used:.1f} s"}
+                      f"+ threshold (numpy FFT, one thread), {t_used:.1f} s",
+            "all_cores": {"value": done_all * T / busy, "unit": "template-s/s", "cores": workers,
+                          "sample": f"{done_all} further fine templates of the same sample split over {workers} "
+                                    f"processes (one thread each), {busy:.1f} s of filtering per process "
+                                    f"({wall:.1f} s wall with process start-up)"},
+            "host": host}
     if ctx is None:
         return base, None
     import torch
