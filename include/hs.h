@@ -299,19 +299,28 @@ int hs_chisq_at_peaks(hs_ctx *ctx, const void *spec, int64_t n, double fs, const
  * stat, or an equal stat and a smaller (tmpl, tick_h, tick_l).  Survivors of
  * every slide are written to out sorted by (slide, tick_h).  bg_counts[e] =
  * number of survivors with slide >= 1 and (double)stat >= (double)edges[e]^2.
+ * Statistic floor: with min_snr_c > 0, pairs with (double)stat <
+ * (double)min_snr_c^2 are not formed at all.  Since a coincidence can only be
+ * removed by a better one, the survivors at or above the floor and every
+ * count at an edge >= min_snr_c are exactly those of the full definition;
+ * coincidences below the floor are absent from out (min_snr_c <= 0: none is
+ * dropped).  This bounds the work of long rings and many slides by the pairs
+ * above the floor.
  *   h, l device hs_trigger [nh], [nl]; ticks in [0, wrap); tmpl in [0, n_tmpl)
  *   edges host float [n_edges]; bg_counts host int64 [n_edges]
  *   out device hs_coinc [cap]; n_out host
- * Requires 0 <= 2 window < wrap, step > 0, 0 < cluster_w < 65536,
- * n_slides >= 0, n_slides * step + 3 wrap < 2^50, 0 <= n_edges <= 4096 and no
- * NaN edge (HS_EINVAL otherwise).
+ * Requires 0 <= 2 window < wrap, step > 0, 0 < cluster_w < 2^31,
+ * ceil(wrap / cluster_w) <= 2^26, 1 <= n_tmpl <= 2^24, n_slides >= 0,
+ * n_slides * step + 3 wrap < 2^50, fewer than 2^32 coincident pairs (above the
+ * floor), 0 <= n_edges <= 4096, no NaN edge, a finite min_snr_c and no edge
+ * below a positive min_snr_c (HS_EINVAL otherwise).
  * Background time is n_slides * wrap ticks (Eq. (6) T_b).
  */
 int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, const hs_trigger *l,
                        int64_t nl, int32_t n_tmpl, int64_t n_slides, int64_t step,
-                       int64_t window, int64_t wrap, int64_t cluster_w, const float *edges,
-                       int32_t n_edges, int64_t *bg_counts, hs_coinc *out, int64_t cap,
-                       int64_t *n_out);
+                       int64_t window, int64_t wrap, int64_t cluster_w, float min_snr_c,
+                       const float *edges, int32_t n_edges, int64_t *bg_counts, hs_coinc *out,
+                       int64_t cap, int64_t *n_out);
 
 /*
  * Stage-1 follow-up (Sec. III): coincidences with (double)stat >= rho_min^2

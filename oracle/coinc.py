@@ -22,6 +22,10 @@ is silent:
 * Background counts: n_b(x) = number of surviving coincidences with k >= 1 and
   rho_c >= x (inclusive), evaluated as float64(stat) >= float64(x)^2;
   T_b = K * T.
+* Statistic floor (optional): coincidences with float64(stat) < float64(floor)^2
+  are discarded before the clustering.  A coincidence is only ever removed by a
+  better one, so the survivors at or above the floor and the counts at edges at
+  or above it are unchanged (pinned against the plain definition in the tests).
 """
 import math
 
@@ -116,7 +120,7 @@ def _cluster_slide(tick_h, stat, tmpl, tick_l, cluster_w, wrap):
 
 
 def timeslide_coinc(h, l, n_slides: int, step: int, window: int, wrap: int, cluster_w: int,
-                    edges, ticks_per_second: int):
+                    edges, ticks_per_second: int, min_snr_c: float = 0.0):
     """Coincidences over slides 0..n_slides, clustered per slide, plus background counts.
 
     ``h`` and ``l`` are dicts with arrays tmpl (int), tick (int64 in [0, wrap)), snr.
@@ -135,6 +139,9 @@ def timeslide_coinc(h, l, n_slides: int, step: int, window: int, wrap: int, clus
     snr_h = np.asarray(h["snr"])[i]
     snr_l = np.asarray(l["snr"])[j]
     stat = coinc_stat(snr_h, snr_l)
+    if min_snr_c > 0:
+        keep = np.asarray(stat, np.float64) >= np.float64(min_snr_c) ** 2
+        i, j, k, snr_h, snr_l, stat = i[keep], j[keep], k[keep], snr_h[keep], snr_l[keep], stat[keep]
     tmpl = h_tmpl[i]
     th = h_tick[i]
     tl = l_tick[j]

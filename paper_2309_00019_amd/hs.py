@@ -73,7 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
         "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
         "hs_chisq_at_peaks": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
-        "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, P, I32, P, P, I64,
+        "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, F, P, I32, P, P, I64,
                                ctypes.POINTER(I64)],
         "hs_followup": [P, P, I64, F, P, I32, P, I32, D, I64, I32, P, P],
         "hs_proposer_features": [P, P, I64, P, I64, P, P, P, I64, P, P, I32, I64, P, P, I32, I64, I64, I64, P],
@@ -385,20 +385,22 @@ def hs_chisq(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, trig, se
 
 
 def hs_timeslide_coinc(ctx: Context, trig_h, trig_l, n_tmpl: int, n_slides: int, step: int, window: int,
-                       wrap: int, cluster_w: int, edges, cap: int = None):
-    """Returns (int32 [n, 10] device tensor of hs_coinc records, int64 numpy background counts)."""
+                       wrap: int, cluster_w: int, edges, cap: int = None, min_snr_c: float = 0.0):
+    """Returns (int32 [n, 10] device tensor of hs_coinc records, int64 numpy background counts).
+    min_snr_c > 0: coincidences with network SNR below it are not formed (exact at and above it)."""
     _dev(trig_h, torch.int32, "trig_h")
     _dev(trig_l, torch.int32, "trig_l")
     edges = np.ascontiguousarray(edges, dtype=np.float32)
     bg = np.zeros(len(edges), np.int64)
     if cap is None:
-        cap = (n_slides + 1) * (wrap // cluster_w + 2)
+        # at most one survivor per (slide, cluster window); grown on overflow beyond 4 M records
+        cap = min((n_slides + 1) * (wrap // cluster_w + 2), 1 << 22)
     for _ in range(2):
         out = torch.empty((max(cap, 1), 10), dtype=torch.int32, device=trig_h.device)
         cnt = ctypes.c_int64(0)
         st = _lib.hs_timeslide_coinc(ctx.handle, _ptr(trig_h), trig_h.shape[0], _ptr(trig_l), trig_l.shape[0],
-                                     n_tmpl, n_slides, step, window, wrap, cluster_w, _ptr(edges), len(edges),
-                                     _ptr(bg), _ptr(out), cap, ctypes.byref(cnt))
+                                     n_tmpl, n_slides, step, window, wrap, cluster_w, float(min_snr_c), _ptr(edges),
+                                     len(edges), _ptr(bg), _ptr(out), cap, ctypes.byref(cnt))
         if st == HS_EOVERFLOW:
             cap = int(cnt.value)
             continue

@@ -42,6 +42,7 @@ class SearchConfig:
     step_sec: float = 0.1
     coinc_window_sec: float = 0.015
     cluster_sec: float = 1.0      # per-slide coincidence clustering window
+    coinc_min_snr: float = 0.0    # background / stage-2 coincidences below this network SNR are not formed
     edges: tuple = tuple(round(6.0 + 0.1 * i, 1) for i in range(81))   # background count grid, 6.0 .. 14.0
     chisq_rho_min: float = 5.5    # triggers at or above this SNR get the chi-square re-weighting (None: off)
     far_x_min: float = 7.0        # Eq. (7) fit over the edges >= far_x_min with non-zero counts
@@ -174,11 +175,11 @@ def background_far(ctx, res: "SearchResult", cfg: SearchConfig):
                 ifar_10yr=hs.hs_far_threshold(a, b, res.t_b, 10 * YEAR))
 
 
-def _coinc(ctx, th, tl, n_tmpl, n_slides, step_sec, cfg, wrap, edges):
+def _coinc(ctx, th, tl, n_tmpl, n_slides, step_sec, cfg, wrap, edges, min_snr_c=0.0):
     tk = cfg.ticks_per_second
     return hs.hs_timeslide_coinc(ctx, th, tl, n_tmpl, n_slides, int(round(step_sec * tk)),
                                  int(round(cfg.coinc_window_sec * tk)), wrap, int(round(cfg.cluster_sec * tk)),
-                                 edges)
+                                 edges, min_snr_c=min_snr_c)
 
 
 def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=False) -> SearchResult:
@@ -192,7 +193,8 @@ def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=
     th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rh)
     tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rl)
     wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
-    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
+    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32),
+                    cfg.coinc_min_snr)
     T = n / cfg.fs
     apps = 2 * n_seg * fine.n_tmpl
     return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,
@@ -257,7 +259,8 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, per_seg, cfg.thr2, cfg, timer, raw_sink=rh)
     tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, per_seg, cfg.thr2, cfg, timer, raw_sink=rl)
     raw.update(h=rh[0], l=rl[0])
-    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32))
+    co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32),
+                    cfg.coinc_min_snr)
     T = n / cfg.fs
     apps = 2 * int(sum(counts))
     return SearchResult(th, tl, co, bg, cfg.n_slides * wrap / cfg.ticks_per_second, apps, apps * T,

@@ -360,6 +360,65 @@ def test_timeslide_coinc_exact_on_identical_inputs(ctx, seed, wrap, K, step, win
     assert np.array_equal(bg, ref["bg_counts"])
 
 
+@pytest.mark.parametrize("min_snr_c", [0.0, 7.0])
+def test_timeslide_coinc_exact_over_a_day_and_100000_slides(ctx, min_snr_c):
+    """The full-background shape: 24 h of ticks (4.4e9, beyond int32), 100,000 slides of 0.1 s,
+    15 ms window, 1 s clustering -- 8.6e9 (slide, tile) bins, processed in batches of slides --
+    and template ids up to 200,000 (beyond 16 bits).  Without a floor every coincidence is
+    formed; with the floor at network SNR 7 only those at or above it, and the oracle's full
+    result restricted to them must come out."""
+    from paper_2309_00019_amd import hs
+    _say(f"coinc 24 h x 100,000 slides floor={min_snr_c}")
+    g = np.random.default_rng(250)
+    wrap, K, step, window, cw = 86400 * 51200, 100_000, 5120, 768, 51200
+    ids = np.sort(g.choice(200_000, 300, replace=False))
+    th = synth.synthetic_triggers(g, 0, wrap, 150, 25, 256 * 51200, snr=(4.0, 9.0), tmpl_ids=ids)
+    tl = synth.synthetic_triggers(g, 0, wrap, 150, 25, 256 * 51200, snr=(4.0, 9.0), tmpl_ids=ids)
+    tl["snr"][::7] = th["snr"][0]  # exact stat ties
+    edges = np.array([7.0, 7.5, 8.0, 9.0, 10.0, 12.0], np.float32)
+    out, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(th, ctx.device), hs.to_device_records(tl, ctx.device),
+                                    200_000, K, step, window, wrap, cw, edges, min_snr_c=min_snr_c)
+    got = hs.as_records(out, hs.COINC)
+    ref = oracle.timeslide_coinc(dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"]),
+                                 dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"]),
+                                 K, step, window, wrap, cw, edges, 51200, min_snr_c=min_snr_c)
+    c = ref["coincs"]
+    _say(f"  {len(got)} coincidences on {len(np.unique(got['slide']))} slides; background counts {list(bg)}")
+    assert len(got) == len(c["slide"]) > 1000
+    for f in ("slide", "tmpl", "tick_h", "tick_l"):
+        assert np.array_equal(got[f], np.asarray(c[f]).astype(got[f].dtype)), f
+    assert np.array_equal(got["stat"], c["stat"])
+    assert np.array_equal(bg, ref["bg_counts"]) and bg[0] > 100
+    assert got["tmpl"].max() > 65536 and got["tick_h"].max() > 2 ** 32 and got["slide"].max() > 90_000
+
+
+@pytest.mark.parametrize("min_snr_c", [0.0, 6.75])
+def test_timeslide_coinc_exact_with_few_long_slides_on_a_day(ctx, min_snr_c):
+    """The stage-1 shape on a day-long ring: 16 slides of 15 s over 24 h, so an H trigger can
+    only meet L triggers within 4 minutes before it; the L triggers are read by time block
+    (1,440 blocks here) and, under a floor, by SNR band."""
+    from paper_2309_00019_amd import hs
+    _say(f"coinc 24 h x 16 slides of 15 s floor={min_snr_c}")
+    g = np.random.default_rng(251)
+    wrap, K, step, window, cw = 86400 * 51200, 16, 15 * 51200, 768, 51200
+    th = synth.synthetic_triggers(g, 10, wrap, 3000, 100, 256 * 51200, snr=(3.5, 8.0))
+    tl = synth.synthetic_triggers(g, 10, wrap, 3000, 100, 256 * 51200, snr=(3.5, 8.0))
+    edges = np.array([6.75, 7.0, 8.0, 10.0], np.float32)
+    out, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(th, ctx.device), hs.to_device_records(tl, ctx.device),
+                                    10, K, step, window, wrap, cw, edges, min_snr_c=min_snr_c)
+    got = hs.as_records(out, hs.COINC)
+    ref = oracle.timeslide_coinc(dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"]),
+                                 dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"]),
+                                 K, step, window, wrap, cw, edges, 51200, min_snr_c=min_snr_c)
+    c = ref["coincs"]
+    _say(f"  {len(got)} coincidences; background counts {list(bg)}")
+    assert len(got) == len(c["slide"]) > 100
+    for f in ("slide", "tmpl", "tick_h", "tick_l"):
+        assert np.array_equal(got[f], np.asarray(c[f]).astype(got[f].dtype)), f
+    assert np.array_equal(got["stat"], c["stat"])
+    assert np.array_equal(bg, ref["bg_counts"])
+
+
 def test_timeslide_coinc_exact_on_crowded_bins(ctx):
     """A glitch-like crowd: thousands of templates coincide within a few clustering tiles of the
     same slides, so bins hold hundreds of pairs and champions must scan neighbour bins whose

@@ -360,3 +360,41 @@ def test_timeslide_coinc_matches_bruteforce_over_many_wraps(seed):
     bg = [stat[p] for p in kept if p[0] >= 1]
     for e, cnt in zip(edges, out["bg_counts"]):
         assert cnt == sum(1 for s in bg if np.float64(s) >= np.float64(e) ** 2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_timeslide_coinc_floor_keeps_everything_at_or_above_it(seed):
+    # the floor only drops coincidences below it: survivors at or above it and counts at edges at
+    # or above it equal those of the plain definition (itself pinned by the brute force above)
+    g = np.random.default_rng(400 + seed)
+    wrap, step, window, cw, K = 40000, 700, 120, int(g.integers(300, 3000)), 50
+    th = synth.synthetic_triggers(g, 5, wrap, 12, 5, wrap, snr=(3.5, 7.5))
+    tl = synth.synthetic_triggers(g, 5, wrap, 12, 5, wrap, snr=(3.5, 7.5))
+    h = dict(tmpl=th["tmpl"], tick=th["tick"], snr=th["snr"])
+    l = dict(tmpl=tl["tmpl"], tick=tl["tick"], snr=tl["snr"])
+    floor = float(g.choice([6.0, 7.0, 8.0]))
+    edges = np.array([floor, floor + 0.5, floor + 1.5, 12.0], np.float32)
+    full = oracle.timeslide_coinc(h, l, K, step, window, wrap, cw, edges, 100)
+    cut = oracle.timeslide_coinc(h, l, K, step, window, wrap, cw, edges, 100, min_snr_c=floor)
+    f, c = full["coincs"], cut["coincs"]
+    keep = np.asarray(f["stat"], np.float64) >= floor ** 2
+    assert 0 < len(c["slide"]) < len(f["slide"]) and np.any(~keep)
+    for k in ("slide", "tmpl", "tick_h", "tick_l", "stat"):
+        assert np.array_equal(np.asarray(f[k])[keep], np.asarray(c[k])), k
+    assert np.array_equal(full["bg_counts"], cut["bg_counts"])
+    # and the brute force with the floor applied to its pairs agrees too
+    small = np.nonzero(th["tmpl"] < 2)[0], np.nonzero(tl["tmpl"] < 2)[0]
+    hs_ = {k: v[small[0]] for k, v in h.items()}
+    ls_ = {k: v[small[1]] for k, v in l.items()}
+    cut2 = oracle.timeslide_coinc(hs_, ls_, 12, step, window, wrap, cw, edges, 100, min_snr_c=floor)
+    pairs, _, stat = _brute_coinc(hs_, ls_, 12, step, window, wrap, cw)
+    pairs = [p for p in pairs if np.float64(stat[p]) >= floor ** 2]
+
+    def key(p):
+        return (stat[p], -hs_["tmpl"][p[1]], -hs_["tick"][p[1]], -ls_["tick"][p[2]])
+    kept = [p for p in pairs if not any(q != p and q[0] == p[0] and key(q) > key(p) and
+            abs((int(hs_["tick"][q[1]]) - int(hs_["tick"][p[1]]) + wrap // 2) % wrap - wrap // 2) <= cw
+            for q in pairs)]
+    got = sorted(zip(cut2["coincs"]["slide"].tolist(), cut2["coincs"]["tick_h"].tolist(),
+                     cut2["coincs"]["tick_l"].tolist()))
+    assert got == sorted((k, int(hs_["tick"][i]), int(ls_["tick"][j])) for k, i, j in kept)
