@@ -46,35 +46,43 @@ def _circ(x, T):
     return (x + T // 2) % T - T // 2
 
 
-def _pairs(h_tmpl, h_tick, l_tmpl, l_tick, n_slides, step, window, wrap):
-    """All (i_H, j_L, k) with equal template and |circ(t_H - t_L - k step)| <= window."""
+def _pairs(h_tmpl, h_tick, l_tmpl, l_tick, n_slides, step, window, wrap, keep_pair=None):
+    """All (i_H, j_L, k) with equal template and |circ(t_H - t_L - k step)| <= window.
+    keep_pair(I, J) -> bool mask restricts the pairs first (the statistic floor)."""
     out_i, out_j, out_k = [], [], []
     l_order = np.argsort(l_tmpl, kind="stable")
     l_sorted = l_tmpl[l_order]
     j_max = (n_slides * step + window) // wrap + 1
     for t in np.unique(h_tmpl):
-        ih = np.nonzero(h_tmpl == t)[0]
+        ih_all = np.nonzero(h_tmpl == t)[0]
         a = np.searchsorted(l_sorted, t, "left")
         b = np.searchsorted(l_sorted, t, "right")
         jl = l_order[a:b]
         if len(jl) == 0:
             continue
-        I = np.repeat(ih, len(jl))
-        J = np.tile(jl, len(ih))
-        d = (h_tick[I] - l_tick[J]) % wrap                        # in [0, T)
-        for j in range(-1, j_max + 1):
-            # k step must lie in [d - window + j T, d + window + j T]
-            k_lo = -((-(d - window + j * wrap)) // step)           # ceil
-            k_hi = (d + window + j * wrap) // step                 # floor
-            k_lo = np.maximum(k_lo, 0)
-            k_hi = np.minimum(k_hi, n_slides)
-            width = int(np.max(k_hi - k_lo + 1)) if len(d) else 0
-            for o in range(max(width, 0)):
-                k = k_lo + o
-                ok = k <= k_hi
-                out_i.append(I[ok])
-                out_j.append(J[ok])
-                out_k.append(k[ok])
+        # H triggers of the template in chunks, so nH x nL never materialises at once
+        chunk = max(1, (1 << 22) // len(jl))
+        for c0 in range(0, len(ih_all), chunk):
+            ih = ih_all[c0:c0 + chunk]
+            I = np.repeat(ih, len(jl))
+            J = np.tile(jl, len(ih))
+            if keep_pair is not None:
+                m = keep_pair(I, J)
+                I, J = I[m], J[m]
+            d = (h_tick[I] - l_tick[J]) % wrap                        # in [0, T)
+            for j in range(-1, j_max + 1):
+                # k step must lie in [d - window + j T, d + window + j T]
+                k_lo = -((-(d - window + j * wrap)) // step)           # ceil
+                k_hi = (d + window + j * wrap) // step                 # floor
+                k_lo = np.maximum(k_lo, 0)
+                k_hi = np.minimum(k_hi, n_slides)
+                width = int(np.max(k_hi - k_lo + 1)) if len(d) else 0
+                for o in range(max(width, 0)):
+                    k = k_lo + o
+                    ok = k <= k_hi
+                    out_i.append(I[ok])
+                    out_j.append(J[ok])
+                    out_k.append(k[ok])
     if not out_i:
         z = np.zeros(0, np.int64)
         return z, z, z
@@ -135,13 +143,15 @@ def timeslide_coinc(h, l, n_slides: int, step: int, window: int, wrap: int, clus
     l_tick = np.asarray(l["tick"], np.int64)
     if np.any((h_tick < 0) | (h_tick >= wrap)) or np.any((l_tick < 0) | (l_tick >= wrap)):
         raise ValueError("trigger ticks must lie in [0, wrap)")
-    i, j, k = _pairs(h_tmpl, h_tick, l_tmpl, l_tick, n_slides, step, window, wrap)
-    snr_h = np.asarray(h["snr"])[i]
-    snr_l = np.asarray(l["snr"])[j]
-    stat = coinc_stat(snr_h, snr_l)
+    hs_, ls_ = np.asarray(h["snr"]), np.asarray(l["snr"])
+    keep = None
     if min_snr_c > 0:
-        keep = np.asarray(stat, np.float64) >= np.float64(min_snr_c) ** 2
-        i, j, k, snr_h, snr_l, stat = i[keep], j[keep], k[keep], snr_h[keep], snr_l[keep], stat[keep]
+        # the floor is a property of the pair alone, so it may be applied before the slides
+        keep = lambda I, J: np.asarray(coinc_stat(hs_[I], ls_[J]), np.float64) >= np.float64(min_snr_c) ** 2
+    i, j, k = _pairs(h_tmpl, h_tick, l_tmpl, l_tick, n_slides, step, window, wrap, keep)
+    snr_h = hs_[i]
+    snr_l = ls_[j]
+    stat = coinc_stat(snr_h, snr_l)
     tmpl = h_tmpl[i]
     th = h_tick[i]
     tl = l_tick[j]

@@ -18,9 +18,10 @@
 // so far, then atomicMin on tick_l -- and only that champion can survive; since the three values
 // describe it completely, every coincidence checks the champions of the neighbouring tiles of its
 // slide itself and marks those it beats within reach (no per-bin lists).
-// The pairs are counting-sorted by slide, and the bins of a batch of consecutive slides (at most
-// CO_BATCH_BINS) are processed at a time, so the slide range and the ring length are bounded only
-// by the pair count; survivors are compacted in bin order, i.e. sorted by (slide, tick_h).
+// When the (slide, tile) bins exceed CO_BATCH_BINS the pairs are counting-sorted by slide and the
+// bins of a batch of consecutive slides are processed at a time, so the slide range and the ring
+// length are bounded only by the pair count; survivors are compacted in bin order, i.e. sorted by
+// (slide, tick_h).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -484,6 +485,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     // (arena growth preserves what was written).
     const int64_t per_batch = CO_BATCH_BINS / n_tiles;  // slides per batch (>= 1)
     const int64_t bb = std::min<int64_t>(per_batch, n_sl) * n_tiles;  // bins of the largest batch
+    const int64_t n_batches = cdiv(n_sl, per_batch);
     RawCoinc *raw, *sorted;
     uint32_t *scnt, *scur, *veto, *flag, *slot, *best_th;
     unsigned long long *best, *best_tl, *bgc;
@@ -493,7 +495,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         Carver cv;
         carve1(cv);
         cv.add(&raw, P);
-        cv.add(&sorted, P);
+        cv.add(&sorted, n_batches > 1 ? P : 1);
         cv.add(&scnt, n_sl);
         cv.add(&scur, n_sl);
         cv.add(&soff, n_sl + 1);
@@ -512,17 +514,16 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     hipLaunchKernelGGL(co_pair_write, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l, n_tmpl, g,
                        lg, floor2, lstart, lidx, poff, raw);
     HS_HIP(hipGetLastError());
-    const unsigned gp = (unsigned)cdiv((int64_t)P, 256);
-    HS_TRY(fill_u32(ctx, scnt, n_sl, 0));
-    HS_TRY(fill_u32(ctx, scur, n_sl, 0));
-    hipLaunchKernelGGL(co_slide_count, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, scnt);
-    HS_HIP(hipGetLastError());
-    HS_TRY(exclusive_scan_u32(ctx, scnt, n_sl, soff, tmp2));
-    hipLaunchKernelGGL(co_slide_scatter, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, soff, scur, sorted);
-    HS_HIP(hipGetLastError());
     std::vector<uint64_t> hsoff;
-    const int64_t n_batches = cdiv(n_sl, per_batch);
-    if (n_batches > 1) {  // pair ranges of the batches
+    if (n_batches > 1) {  // pairs in slide order, and the pair range of every batch
+        const unsigned gp = (unsigned)cdiv((int64_t)P, 256);
+        HS_TRY(fill_u32(ctx, scnt, n_sl, 0));
+        HS_TRY(fill_u32(ctx, scur, n_sl, 0));
+        hipLaunchKernelGGL(co_slide_count, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, scnt);
+        HS_HIP(hipGetLastError());
+        HS_TRY(exclusive_scan_u32(ctx, scnt, n_sl, soff, tmp2));
+        hipLaunchKernelGGL(co_slide_scatter, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, soff, scur, sorted);
+        HS_HIP(hipGetLastError());
         hsoff.resize(n_sl + 1);
         HS_TRY(read_back(ctx, soff, hsoff.data(), (n_sl + 1) * sizeof(uint64_t)));
     }
@@ -550,7 +551,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         if (q1 == q0) continue;
         const int64_t nb = (k1 - k0) * n_tiles;
         const int64_t Pb = (int64_t)(q1 - q0);
-        const RawCoinc *rb = sorted + q0;
+        const RawCoinc *rb = (n_batches > 1 ? sorted : raw) + q0;
         BinGeom bgm{cluster_w, n_tiles, k0, 1.0 / (double)cluster_w};
         const unsigned gq = (unsigned)cdiv(Pb, 256);
         HS_TRY(fill_u32(ctx, veto, nb, 0));

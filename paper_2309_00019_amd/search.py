@@ -43,6 +43,7 @@ class SearchConfig:
     coinc_window_sec: float = 0.015
     cluster_sec: float = 1.0      # per-slide coincidence clustering window
     coinc_min_snr: float = 0.0    # background / stage-2 coincidences below this network SNR are not formed
+    stage1_min_snr: float = 0.0   # stage-1 coincidences below this are not formed (at most the follow-up bar)
     edges: tuple = tuple(round(6.0 + 0.1 * i, 1) for i in range(81))   # background count grid, 6.0 .. 14.0
     chisq_rho_min: float = 5.5    # triggers at or above this SNR get the chi-square re-weighting (None: off)
     far_x_min: float = 7.0        # Eq. (7) fit over the edges >= far_x_min with non-zero counts
@@ -217,7 +218,7 @@ def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=Non
         raw.update(h1=rh[0], l1=rl[0])
     wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
     c1, _ = _coinc(ctx, th[0] if with_chisq else th, tl[0] if with_chisq else tl, coarse_h.n_tmpl, cfg.n_sh1,
-                   cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32))
+                   cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32), cfg.stage1_min_snr)
     return th, tl, c1
 
 
