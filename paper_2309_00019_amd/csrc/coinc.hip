@@ -18,10 +18,10 @@
 // so far, then atomicMin on tick_l -- and only that champion can survive; since the three values
 // describe it completely, every coincidence checks the champions of the neighbouring tiles of its
 // slide itself and marks those it beats within reach (no per-bin lists).
-// When the (slide, tile) bins exceed CO_BATCH_BINS the pairs are counting-sorted by slide and the
-// bins of a batch of consecutive slides are processed at a time, so the slide range and the ring
-// length are bounded only by the pair count; survivors are compacted in bin order, i.e. sorted by
-// (slide, tick_h).
+// When the (slide, tile) bins exceed CO_BATCH_BINS the pairs are written in slide order (per-slide
+// counts from the counting pass, per-slide cursors in the writing pass) and the bins of a batch of
+// consecutive slides are processed at a time, so the slide range and the ring length are bounded
+// only by the pair count; survivors are compacted in bin order, i.e. sorted by (slide, tick_h).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -166,11 +166,13 @@ __device__ __forceinline__ void for_each_partner(const hs_trigger &a, const hs_t
     }
 }
 
+// Pairs per H trigger and, when the bins need several batches of slides (scnt non-null), per
+// slide as well.
 __global__ void co_pair_count(const hs_trigger *__restrict__ h, int64_t nh, const hs_trigger *__restrict__ l,
                               int32_t n_tmpl, SlideGeom g, LGroups lg, double stat2_min,
                               const uint64_t *__restrict__ lstart,
                               const uint32_t *__restrict__ lidx, uint32_t *__restrict__ pc,
-                              int32_t *__restrict__ bad) {
+                              uint32_t *__restrict__ scnt, int32_t *__restrict__ bad) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nh) return;
     const hs_trigger a = h[i];
@@ -181,42 +183,38 @@ __global__ void co_pair_count(const hs_trigger *__restrict__ h, int64_t nh, cons
         for_each_partner(a, l, lstart, lidx, lg, g, stat2_min, [&](uint32_t, const hs_trigger &b, float) {
             int64_t d = a.tick - b.tick;  // both ticks in [0, wrap)
             if (d < 0) d += g.wrap;
-            for_each_slide(d, g, [&](int64_t) { ++c; });
+            for_each_slide(d, g, [&](int64_t k) {
+                ++c;
+                if (scnt) atomicAdd(&scnt[k], 1u);
+            });
         });
     }
     pc[i] = c;
 }
 
+// The pairs, written at per-H-trigger offsets (one batch of slides) or straight into slide order
+// through per-slide cursors (several batches; the order within a slide is unspecified and nothing
+// downstream depends on it).
+template <bool BY_SLIDE>
 __global__ void co_pair_write(const hs_trigger *__restrict__ h, int64_t nh, const hs_trigger *__restrict__ l,
                               int32_t n_tmpl, SlideGeom g, LGroups lg, double stat2_min,
-                              const uint64_t *__restrict__ lstart,
-                              const uint32_t *__restrict__ lidx, const uint64_t *__restrict__ poff,
-                              RawCoinc *__restrict__ raw) {
+                              const uint64_t *__restrict__ lstart, const uint32_t *__restrict__ lidx,
+                              const uint64_t *__restrict__ poff, const uint64_t *__restrict__ soff,
+                              uint32_t *__restrict__ scur, RawCoinc *__restrict__ raw) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nh) return;
     const hs_trigger a = h[i];
     if (!trig_ok(a, n_tmpl, g.wrap)) return;
-    uint64_t w = poff[i];
+    uint64_t w = BY_SLIDE ? 0 : poff[i];
     for_each_partner(a, l, lstart, lidx, lg, g, stat2_min, [&](uint32_t jl, const hs_trigger &b, float stat) {
         int64_t d = a.tick - b.tick;  // both ticks in [0, wrap)
         if (d < 0) d += g.wrap;
-        for_each_slide(d, g, [&](int64_t k) { raw[w++] = RawCoinc{(uint32_t)i, jl, (uint32_t)k, stat}; });
+        for_each_slide(d, g, [&](int64_t k) {
+            const RawCoinc r{(uint32_t)i, jl, (uint32_t)k, stat};
+            if (BY_SLIDE) raw[soff[k] + atomicAdd(&scur[k], 1u)] = r;
+            else raw[w++] = r;
+        });
     });
-}
-
-// Counting sort of the pairs by slide (order within a slide is unspecified: nothing downstream
-// depends on it).
-__global__ void co_slide_count(const RawCoinc *__restrict__ raw, int64_t P, uint32_t *__restrict__ cnt) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q < P) atomicAdd(&cnt[raw[q].k], 1u);
-}
-
-__global__ void co_slide_scatter(const RawCoinc *__restrict__ raw, int64_t P, const uint64_t *__restrict__ start,
-                                 uint32_t *__restrict__ cursor, RawCoinc *__restrict__ out) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= P) return;
-    const RawCoinc r = raw[q];
-    out[start[r.k] + atomicAdd(&cursor[r.k], 1u)] = r;
 }
 
 // Champion of a bin, first pass: the statistic, then the smaller template.  Never 0 for a real
@@ -440,10 +438,18 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     }
     const int64_t n_groups = (int64_t)n_tmpl * lg.n_bands * lg.n_blocks;
 
+    // (slide, tile) bins are processed in batches of whole slides; with several batches the pairs
+    // are written in slide order
+    const int64_t per_batch = CO_BATCH_BINS / n_tiles;  // slides per batch (>= 1)
+    const int64_t bb = std::min<int64_t>(per_batch, n_sl) * n_tiles;  // bins of the largest batch
+    const int64_t n_batches = cdiv(n_sl, per_batch);
+    const bool by_slide = n_batches > 1;
+
     // --- phase 1: group L by (template, SNR^2 band, time block), count pairs per H trigger ----
-    uint32_t *lcnt, *lcur, *lidx, *pc;
-    uint64_t *lstart, *poff, *tmp1;
+    uint32_t *lcnt, *lcur, *lidx, *pc, *scnt, *scur;
+    uint64_t *lstart, *poff, *soff, *tmp1;
     int32_t *bad;
+    const int64_t n_scan1 = std::max<int64_t>(std::max<int64_t>(nh, n_groups), by_slide ? n_sl : 1);
     auto carve1 = [&](Carver &cv) {
         cv.add(&lcnt, n_groups);
         cv.add(&lcur, n_groups);
@@ -451,7 +457,10 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         cv.add(&lidx, nl);
         cv.add(&pc, nh);
         cv.add(&poff, nh + 1);
-        cv.add(&tmp1, scan_tmp_elems(nh > n_groups ? nh : n_groups));
+        cv.add(&scnt, by_slide ? n_sl : 1);
+        cv.add(&scur, by_slide ? n_sl : 1);
+        cv.add(&soff, by_slide ? n_sl + 1 : 1);
+        cv.add(&tmp1, scan_tmp_elems(n_scan1));
         cv.add(&bad, 1);
     };
     {
@@ -462,6 +471,10 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     HS_TRY(fill_u32(ctx, lcnt, n_groups, 0));
     HS_TRY(fill_u32(ctx, lcur, n_groups, 0));
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
+    if (by_slide) {
+        HS_TRY(fill_u32(ctx, scnt, n_sl, 0));
+        HS_TRY(fill_u32(ctx, scur, n_sl, 0));
+    }
     hipLaunchKernelGGL(co_group_count, dim3((unsigned)cdiv(nl, 256)), dim3(256), 0, ctx->stream, l, nl, n_tmpl, wrap,
                        lg, lcnt, bad);
     HS_HIP(hipGetLastError());
@@ -469,7 +482,7 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     hipLaunchKernelGGL(co_group_scatter, dim3((unsigned)cdiv(nl, 256)), dim3(256), 0, ctx->stream, l, nl, n_tmpl,
                        wrap, lg, lstart, lcur, lidx);
     hipLaunchKernelGGL(co_pair_count, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l, n_tmpl, g,
-                       lg, floor2, lstart, lidx, pc, bad);
+                       lg, floor2, lstart, lidx, pc, by_slide ? scnt : nullptr, bad);
     HS_HIP(hipGetLastError());
     HS_TRY(exclusive_scan_u32(ctx, pc, nh, poff, tmp1));
     uint64_t P = 0;
@@ -480,25 +493,18 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     HS_REQUIRE(P < (uint64_t(1) << 32), "hs_timeslide_coinc: %llu coincident pairs exceed 2^32",
                (unsigned long long)P);
 
-    // --- phase 2: materialise the pairs, counting-sort them by slide ---------------------------
+    // --- phase 2: materialise the pairs (in slide order when there are several batches) ------
     // Phase-1 buffers are re-carved first, in the same order, so they keep their contents
     // (arena growth preserves what was written).
-    const int64_t per_batch = CO_BATCH_BINS / n_tiles;  // slides per batch (>= 1)
-    const int64_t bb = std::min<int64_t>(per_batch, n_sl) * n_tiles;  // bins of the largest batch
-    const int64_t n_batches = cdiv(n_sl, per_batch);
-    RawCoinc *raw, *sorted;
-    uint32_t *scnt, *scur, *veto, *flag, *slot, *best_th;
+    RawCoinc *raw;
+    uint32_t *veto, *flag, *slot, *best_th;
     unsigned long long *best, *best_tl, *bgc;
-    uint64_t *soff, *boff, *tmp2;
+    uint64_t *boff, *tmp2;
     double *e2;
     {
         Carver cv;
         carve1(cv);
         cv.add(&raw, P);
-        cv.add(&sorted, n_batches > 1 ? P : 1);
-        cv.add(&scnt, n_sl);
-        cv.add(&scur, n_sl);
-        cv.add(&soff, n_sl + 1);
         cv.add(&veto, bb);
         cv.add(&flag, bb);
         cv.add(&slot, bb);
@@ -506,27 +512,24 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
         cv.add(&best, bb);
         cv.add(&best_tl, bb);
         cv.add(&boff, bb + 1);
-        cv.add(&tmp2, scan_tmp_elems(bb > n_sl ? bb : n_sl));
+        cv.add(&tmp2, scan_tmp_elems(bb));
         cv.add(&e2, n_edges > 0 ? n_edges : 1);
         cv.add(&bgc, n_edges + 1);
         HS_TRY(cv.commit(ctx));
     }
-    hipLaunchKernelGGL(co_pair_write, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l, n_tmpl, g,
-                       lg, floor2, lstart, lidx, poff, raw);
-    HS_HIP(hipGetLastError());
     std::vector<uint64_t> hsoff;
-    if (n_batches > 1) {  // pairs in slide order, and the pair range of every batch
-        const unsigned gp = (unsigned)cdiv((int64_t)P, 256);
-        HS_TRY(fill_u32(ctx, scnt, n_sl, 0));
-        HS_TRY(fill_u32(ctx, scur, n_sl, 0));
-        hipLaunchKernelGGL(co_slide_count, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, scnt);
-        HS_HIP(hipGetLastError());
-        HS_TRY(exclusive_scan_u32(ctx, scnt, n_sl, soff, tmp2));
-        hipLaunchKernelGGL(co_slide_scatter, dim3(gp), dim3(256), 0, ctx->stream, raw, (int64_t)P, soff, scur, sorted);
-        HS_HIP(hipGetLastError());
+    if (by_slide) {
+        HS_TRY(exclusive_scan_u32(ctx, scnt, n_sl, soff, tmp1));
         hsoff.resize(n_sl + 1);
         HS_TRY(read_back(ctx, soff, hsoff.data(), (n_sl + 1) * sizeof(uint64_t)));
+        HS_REQUIRE(hsoff[n_sl] == P, "hs_timeslide_coinc: internal pair count mismatch");
+        hipLaunchKernelGGL(co_pair_write<true>, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l,
+                           n_tmpl, g, lg, floor2, lstart, lidx, poff, soff, scur, raw);
+    } else {
+        hipLaunchKernelGGL(co_pair_write<false>, dim3((unsigned)cdiv(nh, 256)), dim3(256), 0, ctx->stream, h, nh, l,
+                           n_tmpl, g, lg, floor2, lstart, lidx, poff, soff, scur, raw);
     }
+    HS_HIP(hipGetLastError());
 
     // thresholds in ascending order (ties keep their order), counted over the batches' bins
     std::vector<double> hs2(n_edges);
@@ -547,11 +550,11 @@ extern "C" int hs_timeslide_coinc(hs_ctx *ctx, const hs_trigger *h, int64_t nh, 
     uint64_t total = 0;
     for (int64_t k0 = 0; k0 < n_sl; k0 += per_batch) {
         const int64_t k1 = std::min(n_sl, k0 + per_batch);
-        const uint64_t q0 = n_batches > 1 ? hsoff[k0] : 0, q1 = n_batches > 1 ? hsoff[k1] : P;
+        const uint64_t q0 = by_slide ? hsoff[k0] : 0, q1 = by_slide ? hsoff[k1] : P;
         if (q1 == q0) continue;
         const int64_t nb = (k1 - k0) * n_tiles;
         const int64_t Pb = (int64_t)(q1 - q0);
-        const RawCoinc *rb = (n_batches > 1 ? sorted : raw) + q0;
+        const RawCoinc *rb = raw + q0;
         BinGeom bgm{cluster_w, n_tiles, k0, 1.0 / (double)cluster_w};
         const unsigned gq = (unsigned)cdiv(Pb, 256);
         HS_TRY(fill_u32(ctx, veto, nb, 0));
