@@ -45,9 +45,12 @@ def parse():
     ap.add_argument("--coarse", type=int, default=1500)
     ap.add_argument("--seconds", type=int, default=256)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--injections", type=int, default=48,
+    ap.add_argument("--injections", type=int, default=340,
                     help="realisations for the missed-injection fractions (untimed)")
     ap.add_argument("--per-seg", type=int, default=6, help="injections per realisation")
+    ap.add_argument("--inj-seed0", type=int, default=50000,
+                    help="first realisation of the campaign (disjoint from the proposer's training, early-stopping, "
+                         "held-out and tuning realisations)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flat", action="store_true")
@@ -102,12 +105,26 @@ def measured_traffic_per_template():
 
 
 def found_injections(coincs_rec, inj_ticks, tol_ticks, snr_c_min=8.0):
-    zl = coincs_rec[(coincs_rec["slide"] == 0) & (coincs_rec["snr_c"] >= snr_c_min)]
-    found = 0
-    for t in inj_ticks:
-        if np.any(np.abs(zl["tick_h"] - t) <= tol_ticks):
-            found += 1
-    return found
+    """Per injection: a zero-lag coincidence within tol of its H arrival at network SNR >= snr_c_min."""
+    zl = coincs_rec[(coincs_rec["slide"] == 0) & (coincs_rec["snr_c"].astype(np.float64) >= snr_c_min)]
+    return np.array([bool(np.any(np.abs(zl["tick_h"] - t) <= tol_ticks)) for t in inj_ticks], bool)
+
+
+def paired_miss_interval(found_ref, found_new, z=1.96):
+    """Extra-missed fraction of a pipeline against a reference on the same injections: (b - c) / n
+    with b = found by the reference only and c = found by the new one only, and its 95 % interval
+    (Wald interval of a paired difference of proportions); plus the exact (Clopper-Pearson) 95 %
+    upper bound of b / n, the fraction the new pipeline loses whatever it gains elsewhere."""
+    from scipy.stats import beta as beta_dist
+    n = len(found_ref)
+    b = int(np.sum(found_ref & ~found_new))
+    c = int(np.sum(found_new & ~found_ref))
+    d = (b - c) / n
+    var = ((b + c) / n - d * d) / n
+    half = z * np.sqrt(max(var, 0.0))
+    ub = float(beta_dist.ppf(0.975, b + 1, n - b)) if b < n else 1.0
+    return {"extra_missed": round(d, 5), "ci95": [round(d - half, 5), round(d + half, 5)],
+            "lost": b, "gained": c, "lost_fraction_upper95": round(ub, 5)}
 
 
 SNR_TOLERANCE = {"f32": 1e-4, "bf16": 4e-3, "f16": 1e-3}   # relative rho, per template storage
@@ -336,41 +353,45 @@ def main():
         return wall, res
 
     def injection_campaign(count, per_seg):
-        """Independent 256 s realisations with ``per_seg`` injections each (network SNR 6-20);
-        every pipeline runs on each; an injection is found by a zero-lag coincidence within 0.1 s
-        of its H arrival with network SNR >= 8."""
+        """Independent 256 s realisations (seed0, seed0 + 1, ...) with ``per_seg`` injections each
+        (network SNR 6-20), made on a host process pool; every pipeline runs on each; an
+        injection is found by a zero-lag coincidence within 0.1 s of its H arrival with network
+        SNR >= 8 (and, separately, at or above the pipeline's IFAR-1yr threshold)."""
+        import multiprocessing as mp
         tick = cfg.ticks_per_second
-        found = {"flat": 0, "hier": 0, "mlp": 0}
-        found_1yr = {"flat": 0, "hier": 0, "mlp": 0}
+        keys = ("flat", "hier", "mlp") if not args.no_flat else ("hier", "mlp")
+        found = {k: [] for k in keys}
+        found_1yr = {k: [] for k in keys}
         followed = {"hier": [], "mlp": []}
 
         def detected_1yr(res, key, t_inj):
-            """Injections with a zero-lag coincidence within 0.1 s at or above the network SNR
-            whose fitted FAR is 1 / yr; the background model is the pipeline's own, from the
-            noise-only segment (slid injections would otherwise pollute their own background)."""
+            """Above the network SNR whose fitted FAR is 1 / yr; the background model is the
+            pipeline's own, from the noise-only segment (slid injections would otherwise pollute
+            their own background)."""
             thr = ifar_thr.get(key)
             if thr is None:
-                return 0
-            rec = hs.as_records(res.coincs, hs.COINC)
-            ok = (rec["slide"] == 0) & (rec["snr_c"].astype(np.float64) >= thr)
-            return int(sum(np.any(np.abs(rec["tick_h"][ok] - t) <= int(0.1 * tick)) for t in t_inj))
-        for r in range(count):
-            sh_, sl_, ip = workload.injection_realisation(100 + r, n, per_seg)
-            specs = [hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, p)[None]
-                     for x, p in ((sh_, psd_h), (sl_, psd_l))]
-            t_inj = np.round(np.asarray(ip["tc_h"]) * tick).astype(np.int64)
-            for key, kw in (("hier", {}), ("mlp", {"proposer": prop})):
-                res = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l, cfg, **kw)
-                found[key] += found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick))
-                found_1yr[key] += detected_1yr(res, key, t_inj)
-                followed[key].append(int(sum(res.followed)))
-            if not args.no_flat:
-                rf = search.flat_search(ctx, specs[0], specs[1], fine_h, fine_l, cfg)
-                found["flat"] += found_injections(hs.as_records(rf.coincs, hs.COINC), t_inj, int(0.1 * tick))
-                found_1yr["flat"] += detected_1yr(rf, "flat", t_inj)
-            if (r + 1) % 8 == 0:
-                log(f"[injections] {r + 1}/{count} realisations done")
-        return found, followed, found_1yr
+                return np.zeros(len(t_inj), bool)
+            return found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick), thr)
+        jobs = [(args.inj_seed0 + r, per_seg, workload.CFG, n, fs, f_low, workload.MC_RANGE, workload.Q_RANGE,
+                 workload.GLITCH_RATE) for r in range(count)]
+        with mp.get_context("spawn").Pool(16, initializer=synth.single_threaded) as pool:
+            for i, (r, (sh_, sl_, ip)) in enumerate(pool.imap(synth.realisation_job, jobs, chunksize=2)):
+                specs = [hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, p)[None]
+                         for x, p in ((sh_, psd_h), (sl_, psd_l))]
+                t_inj = np.round(np.asarray(ip["tc_h"]) * tick).astype(np.int64)
+                for key in keys:
+                    if key == "flat":
+                        res = search.flat_search(ctx, specs[0], specs[1], fine_h, fine_l, cfg)
+                    else:
+                        res = search.hierarchical_search(ctx, specs[0], specs[1], coarse_h, coarse_l, fine_h, fine_l,
+                                                         cfg, **({"proposer": prop} if key == "mlp" else {}))
+                        followed[key].append(int(sum(res.followed)))
+                    found[key].append(found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick)))
+                    found_1yr[key].append(detected_1yr(res, key, t_inj))
+                if (i + 1) % 20 == 0:
+                    log(f"[injections] {i + 1}/{count} realisations done")
+        cat = lambda d: {k: np.concatenate(v) for k, v in d.items()}
+        return cat(found), followed, cat(found_1yr)
 
     if args.only == "flat":
         wall_f, res_f = timed(step_flat, "flat")
@@ -466,21 +487,26 @@ def main():
         n_inj = args.injections * args.per_seg
         log(f"[injections] {args.injections} realisations x {args.per_seg} (untimed)")
         found, followed, found_1yr = injection_campaign(args.injections, args.per_seg)
-        inj_out = {"n": n_inj, "found_mlp": found["mlp"], "found_hier": found["hier"],
-                   "missed_mlp": round(1 - found["mlp"] / n_inj, 4),
-                   "missed_hier": round(1 - found["hier"] / n_inj, 4),
+        inj_out = {"n": n_inj, "realisations": f"{args.inj_seed0}..{args.inj_seed0 + args.injections - 1}",
+                   "found_mlp": int(found["mlp"].sum()), "found_hier": int(found["hier"].sum()),
+                   "missed_mlp": round(1 - found["mlp"].sum() / n_inj, 4),
+                   "missed_hier": round(1 - found["hier"].sum() / n_inj, 4),
                    "followed_templates_mean_mlp": round(float(np.mean(followed["mlp"])), 1),
-                   "followed_templates_mean_hier": round(float(np.mean(followed["hier"])), 1)}
-        inj_out["detected_ifar_1yr_mlp"] = found_1yr["mlp"]
-        inj_out["detected_ifar_1yr_hier"] = found_1yr["hier"]
+                   "followed_templates_mean_hier": round(float(np.mean(followed["hier"])), 1),
+                   "detected_ifar_1yr_mlp": int(found_1yr["mlp"].sum()),
+                   "detected_ifar_1yr_hier": int(found_1yr["hier"].sum())}
         if not args.no_flat:
-            inj_out["detected_ifar_1yr_flat"] = found_1yr["flat"]
-            if found_1yr["flat"]:
-                inj_out["sensitivity_ratio_ifar_1yr_mlp_vs_flat"] = round(found_1yr["mlp"] / found_1yr["flat"], 4)
-            inj_out["found_flat"] = found["flat"]
-            inj_out["missed_flat"] = round(1 - found["flat"] / n_inj, 4)
-            inj_out["extra_missed_fraction"] = round((found["flat"] - found["mlp"]) / n_inj, 4)
-            inj_out["extra_missed_fraction_plain_hier"] = round((found["flat"] - found["hier"]) / n_inj, 4)
+            inj_out["detected_ifar_1yr_flat"] = int(found_1yr["flat"].sum())
+            if found_1yr["flat"].sum():
+                inj_out["sensitivity_ratio_ifar_1yr_mlp_vs_flat"] = round(found_1yr["mlp"].sum() /
+                                                                          found_1yr["flat"].sum(), 4)
+            inj_out["found_flat"] = int(found["flat"].sum())
+            inj_out["missed_flat"] = round(1 - found["flat"].sum() / n_inj, 4)
+            inj_out["extra_missed_fraction"] = round(float((found["flat"].sum() - found["mlp"].sum()) / n_inj), 4)
+            inj_out["extra_missed_fraction_plain_hier"] = round(float((found["flat"].sum() - found["hier"].sum())
+                                                                      / n_inj), 4)
+            inj_out["extra_missed_mlp_vs_flat"] = paired_miss_interval(found["flat"], found["mlp"])
+            inj_out["extra_missed_plain_vs_flat"] = paired_miss_interval(found["flat"], found["hier"])
         out["injections"] = inj_out
     if not args.no_cpu:
         log("[cpu] timing the oracle on a bounded sample")
