@@ -22,6 +22,7 @@ NumPy/SciPy, citing the passage of the paper it follows:
 * ``proposer``  -- learned follow-up proposer: coincidence features, MLP forward/backward,
                    Adam, cell selection and the cell-restricted neighbourhood rule
 * ``farfit``    -- background tail fit and extrapolated FAR (Sec. IV, Eqs. (6)-(7))
+* ``segments``  -- blocks cut into overlapping segments: valid regions, per-block PSD (Sec. V)
 
 Where the paper is silent or garbled the reading taken is stated in the
 docstring of the function that takes it.
@@ -44,5 +45,7 @@ __all__ = [
 from .chisq import chisq_bin_edges, chisq_at, bin_snrs, chisq_terms, reweighted_snr  # noqa: E402
 from . import proposer  # noqa: E402
 from . import farfit  # noqa: E402
+from . import segments  # noqa: E402
 
-__all__ += ["chisq_bin_edges", "chisq_at", "bin_snrs", "chisq_terms", "reweighted_snr", "proposer", "farfit"]
+__all__ += ["chisq_bin_edges", "chisq_at", "bin_snrs", "chisq_terms", "reweighted_snr", "proposer", "farfit",
+            "segments"]

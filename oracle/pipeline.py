@@ -14,7 +14,11 @@ full-rate transform of the same segment (same df), and the stage-1 PSD the
 leading bins of the full-rate PSD.
 
 A run is ``n_seg`` segments of ``n`` samples laid back to back: sample m of
-segment s has tick s * seg_ticks + m * ticks_per_sample.
+segment s has tick s * seg_ticks + m * ticks_per_sample.  With pads (``segments``:
+overlapping segments of a block, each keeping only its valid region), segments start
+every stride = n - pad_lo - pad_hi samples, only samples pad_lo <= m < n - pad_hi are
+candidates, sample m of segment s has tick (s * stride + m - pad_lo) * ticks_per_sample and
+the timeline (the slide ring and the follow-up's segment of a tick) has stride-long segments.
 """
 import numpy as np
 
@@ -24,6 +28,7 @@ from .coinc import timeslide_coinc
 from .followup import followup_templates
 from .filter import band_edges, template_sigma
 from .chisq import chisq_bin_edges, bin_snrs, chisq_terms, reweighted_snr
+from .segments import valid_mask
 from . import proposer as _proposer
 
 
@@ -58,9 +63,10 @@ def reweight_triggers(tr, st, psd, n, fs, f_low, bank, chisq_bins: int, rho_min:
 
 def detector_triggers(segments, psds, fs: float, f_low: float, bank, tmpl_ids_per_seg, thr: float,
                       window_sec: float, ticks_per_second: int, decim: int = 1, chisq_bins: int = 8,
-                      chisq_rho_min: float = None):
+                      chisq_rho_min: float = None, pad_lo: int = 0, pad_hi: int = 0):
     """Triggers of one detector over all segments.  ``decim`` > 1 filters at fs/decim.
-    With ``chisq_rho_min`` set, snr is the re-weighted SNR of Eq. (4)."""
+    With ``chisq_rho_min`` set, snr is the re-weighted SNR of Eq. (4).  pad_lo / pad_hi (full-rate
+    samples, multiples of decim) restrict candidates to the valid region (``segments`` module)."""
     out = []
     for s, seg in enumerate(segments):
         n_full = len(seg)
@@ -70,25 +76,27 @@ def detector_triggers(segments, psds, fs: float, f_low: float, bank, tmpl_ids_pe
         psd = psds[s][: n // 2 + 1]
         ids = np.asarray(tmpl_ids_per_seg[s], np.int64)
         c = filter_bank(st, psd, n, f, f_low, bank, ids, thr)
+        keep = valid_mask(c["m"], n, pad_lo // decim, pad_hi // decim)
+        c = {k: (v[keep] if k != "sigma" else v) for k, v in c.items()}
         tps = int(round(ticks_per_second / f))
-        seg_ticks = n_full * int(round(ticks_per_second / fs))
+        stride = n_full - pad_lo - pad_hi
+        seg_t0 = (s * stride - pad_lo) * int(round(ticks_per_second / fs))
         tr = triggers_from_candidates(c["tpos"], c["m"], c["rho2"], c["phase"], ids,
-                                      int(round(window_sec * f)), s, s * seg_ticks, tps)
+                                      int(round(window_sec * f)), s, seg_t0, tps)
         if chisq_rho_min is not None:
-            tr = reweight_triggers(tr, st, psd, n, f, f_low, bank, chisq_bins, chisq_rho_min, tps, s * seg_ticks)
+            tr = reweight_triggers(tr, st, psd, n, f, f_low, bank, chisq_bins, chisq_rho_min, tps, seg_t0)
         out.append(tr)
     return _concat(out)
 
 
 def flat_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, bank, thr=4.0, window_sec=1.0,
                 ticks_per_second=51200, n_slides=2000, step_sec=0.1, coinc_window_sec=0.015,
-                cluster_sec=1.0, edges=(8.0,), chisq_bins=8, chisq_rho_min=None):
+                cluster_sec=1.0, edges=(8.0,), chisq_bins=8, chisq_rho_min=None, pad_lo=0, pad_hi=0):
     ids = [np.arange(bank.n_tmpl)] * len(h_segments)
-    th = detector_triggers(h_segments, h_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second,
-                           chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
-    tl = detector_triggers(l_segments, l_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second,
-                           chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
-    wrap = len(h_segments) * len(h_segments[0]) * int(round(ticks_per_second / fs))
+    kw = dict(chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min, pad_lo=pad_lo, pad_hi=pad_hi)
+    th = detector_triggers(h_segments, h_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second, **kw)
+    tl = detector_triggers(l_segments, l_psds, fs, f_low, bank, ids, thr, window_sec, ticks_per_second, **kw)
+    wrap = len(h_segments) * (len(h_segments[0]) - pad_lo - pad_hi) * int(round(ticks_per_second / fs))
     co = timeslide_coinc(th, tl, n_slides, int(round(step_sec * ticks_per_second)),
                          int(round(coinc_window_sec * ticks_per_second)), wrap,
                          int(round(cluster_sec * ticks_per_second)), np.asarray(edges, np.float32),
@@ -100,7 +108,7 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
                         decim=4, thr1=3.5, thr2=4.0, window_sec=1.0, ticks_per_second=51200,
                         n_sh1=16, t_sh1_sec=15.0, rho1=7.0, mc_frac=0.05,
                         n_slides=2000, step_sec=0.1, coinc_window_sec=0.015, cluster_sec=1.0,
-                        edges=(8.0,), chisq_bins=8, chisq_rho_min=None, proposer=None):
+                        edges=(8.0,), chisq_bins=8, chisq_rho_min=None, proposer=None, pad_lo=0, pad_hi=0):
     """``proposer`` = (model, q_edges, p_cum[, rho_low, p_cum_low]) switches the follow-up to the
     learned cell rule (``proposer`` module): coincidences with rho_c >= rho1 keep the cells of
     cumulative probability p_cum, those with rho_low <= rho_c < rho1 the cells of p_cum_low; the
@@ -108,13 +116,13 @@ def hierarchical_search(h_segments, l_segments, h_psds, l_psds, fs, f_low, coars
     n_seg = len(h_segments)
     n_full = len(h_segments[0])
     tpt = int(round(ticks_per_second / fs))
-    seg_ticks = n_full * tpt
+    seg_ticks = (n_full - pad_lo - pad_hi) * tpt          # one segment's share of the timeline
     wrap = n_seg * seg_ticks
     win = int(round(coinc_window_sec * ticks_per_second))
     cw = int(round(cluster_sec * ticks_per_second))
     e = np.asarray(edges, np.float32)
     ids1 = [np.arange(coarse.n_tmpl)] * n_seg
-    kw = dict(chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min)
+    kw = dict(chisq_bins=chisq_bins, chisq_rho_min=chisq_rho_min, pad_lo=pad_lo, pad_hi=pad_hi)
     t1h = detector_triggers(h_segments, h_psds, fs, f_low, coarse, ids1, thr1, window_sec,
                             ticks_per_second, decim, **kw)
     t1l = detector_triggers(l_segments, l_psds, fs, f_low, coarse, ids1, thr1, window_sec,
