@@ -239,18 +239,22 @@ int hs_snr_series(hs_ctx *ctx, const void *spec, int64_t n, double fs, const hs_
 
 /*
  * Peak clustering (Sec. II: a trigger is the peak of the SNR; rule not given,
- * reading): candidate m of template position p survives iff every other
- * candidate m' of p with |m' - m| <= window has rho2' < rho2, or rho2' == rho2
- * and m' > m.  Survivors are written as triggers
- *   {seg, tmpl_ids[p], seg_t0 + m * ticks_per_sample, sqrt(rho2), phase}
- * sorted by (p, m).  Candidates must have distinct (tpos, m), 0 <= m < n,
- * 0 <= tpos < n_ids.
+ * reading): among the candidates of the valid region m_lo <= m < m_hi,
+ * candidate m of template position p survives iff every other such candidate
+ * m' of p with |m' - m| <= window has rho2' < rho2, or rho2' == rho2 and
+ * m' > m.  Candidates outside the valid region are ignored (a segment that
+ * overlaps its neighbours keeps only the samples its circular transform gets
+ * right, Sec. V; m_lo = 0, m_hi = n keeps all).  Survivors are written as
+ * triggers {seg, tmpl_ids[p], seg_t0 + m * ticks_per_sample, sqrt(rho2), phase}
+ * sorted by (p, m); seg_t0 may be negative (only valid samples are emitted).
+ * Candidates must have distinct (tpos, m), 0 <= m < n, 0 <= tpos < n_ids;
+ * HS_EINVAL unless 0 <= m_lo <= m_hi <= n.
  *   cand device [n_cand]; tmpl_ids device [n_ids]; out device [cap]; n_out host.
  */
 int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, int64_t n,
-                        const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int32_t seg,
-                        int64_t seg_t0, int64_t ticks_per_sample, hs_trigger *out, int64_t cap,
-                        int64_t *n_out);
+                        const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int64_t m_lo,
+                        int64_t m_hi, int32_t seg, int64_t seg_t0, int64_t ticks_per_sample,
+                        hs_trigger *out, int64_t cap, int64_t *n_out);
 
 /*
  * Power-consistency chi-square and re-weighted SNR of Sec. II, Eq. (4).  For every

@@ -13,7 +13,8 @@
 // check that itself against the champions of its two neighbour tiles (the champion's m is the low
 // half of its key), marking the ones it beats.  Survivors occupy at most one slot per
 // (template, tile); compacting the slots in bin order yields triggers sorted by (template
-// position, m) with no sort.
+// position, m) with no sort.  Only candidates of the valid region [m_lo, m_hi) take part (a
+// segment that overlaps its neighbours keeps the samples its circular transform gets right).
 #include "hs_internal.h"
 
 namespace hs {
@@ -34,18 +35,19 @@ __device__ __forceinline__ bool cand_ok(const hs_candidate &c, int32_t n_ids, in
 // atomic, and only when the bin's current value does not already beat it (values only grow, so a
 // stale read, atomic like the updates, can only let a useless atomic through).
 __global__ __launch_bounds__(256) void clu_best(const hs_candidate *__restrict__ cand, int64_t n_cand,
-                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles,
-                                                unsigned long long *__restrict__ best, int32_t *__restrict__ bad) {
+                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles, int64_t m_lo,
+                                                int64_t m_hi, unsigned long long *__restrict__ best,
+                                                int32_t *__restrict__ bad) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t b = -1;
     unsigned long long k = 0;
     if (i < n_cand) {
         const hs_candidate c = cand[i];
-        if (cand_ok(c, n_ids, n)) {
+        if (!cand_ok(c, n_ids, n)) {
+            atomicOr(bad, 1);
+        } else if ((int64_t)c.m >= m_lo && (int64_t)c.m < m_hi) {
             b = (int32_t)((int64_t)c.tpos * n_tiles + (uint32_t)c.m / (uint32_t)W);
             k = cand_key(c.rho2, c.m);
-        } else {
-            atomicOr(bad, 1);
         }
     }
     const int lane = threadIdx.x & 63;
@@ -64,13 +66,13 @@ __global__ __launch_bounds__(256) void clu_best(const hs_candidate *__restrict__
 // Champion slots and vetoes: the candidate holding its bin's maximum records its index; every
 // candidate marks the champion of a neighbour tile that lies within W and has a smaller key.
 __global__ __launch_bounds__(256) void clu_veto(const hs_candidate *__restrict__ cand, int64_t n_cand,
-                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles,
-                                                const unsigned long long *__restrict__ best,
+                                                int32_t n_ids, int64_t n, int64_t W, int64_t n_tiles, int64_t m_lo,
+                                                int64_t m_hi, const unsigned long long *__restrict__ best,
                                                 uint32_t *__restrict__ slot, uint32_t *__restrict__ veto) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n_cand) return;
     const hs_candidate c = cand[i];
-    if (!cand_ok(c, n_ids, n)) return;
+    if (!cand_ok(c, n_ids, n) || (int64_t)c.m < m_lo || (int64_t)c.m >= m_hi) return;
     const int64_t tile = (uint32_t)c.m / (uint32_t)W;
     const int64_t b = (int64_t)c.tpos * n_tiles + tile;
     const uint64_t key = cand_key(c.rho2, c.m);
@@ -115,13 +117,15 @@ __global__ void clu_emit(const hs_candidate *__restrict__ cand, int64_t bins, co
 using namespace hs;
 
 extern "C" int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_t n_cand, int64_t n,
-                                   const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int32_t seg,
-                                   int64_t seg_t0, int64_t ticks_per_sample, hs_trigger *out, int64_t cap,
-                                   int64_t *n_out) {
+                                   const int32_t *tmpl_ids, int32_t n_ids, int64_t window, int64_t m_lo,
+                                   int64_t m_hi, int32_t seg, int64_t seg_t0, int64_t ticks_per_sample,
+                                   hs_trigger *out, int64_t cap, int64_t *n_out) {
     HS_REQUIRE(ctx && n_out, "hs_cluster_triggers: null argument");
     HS_REQUIRE(n_cand >= 0 && n > 0 && n_ids >= 0 && window >= 1 && cap >= 0,
                "hs_cluster_triggers: bad sizes (n_cand=%lld n=%lld n_ids=%d window=%lld)", (long long)n_cand,
                (long long)n, n_ids, (long long)window);
+    HS_REQUIRE(m_lo >= 0 && m_lo <= m_hi && m_hi <= n, "hs_cluster_triggers: valid region [%lld, %lld) outside [0, %lld]",
+               (long long)m_lo, (long long)m_hi, (long long)n);
     HS_REQUIRE(n_cand < (int64_t(1) << 32) && n <= (int64_t(1) << 30), "hs_cluster_triggers: input too large");
     *n_out = 0;
     if (n_cand == 0 || n_ids == 0) return HS_OK;
@@ -152,10 +156,10 @@ extern "C" int hs_cluster_triggers(hs_ctx *ctx, const hs_candidate *cand, int64_
     HS_TRY(fill_u32(ctx, reinterpret_cast<uint32_t *>(bad), 1, 0));
     const unsigned gc = (unsigned)cdiv(n_cand, 256);
     const unsigned gb = (unsigned)cdiv(bins, 256);
-    hipLaunchKernelGGL(clu_best, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, best,
-                       bad);
-    hipLaunchKernelGGL(clu_veto, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, best,
-                       slot, veto);
+    hipLaunchKernelGGL(clu_best, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, m_lo,
+                       m_hi, best, bad);
+    hipLaunchKernelGGL(clu_veto, dim3(gc), dim3(256), 0, ctx->stream, cand, n_cand, n_ids, n, window, n_tiles, m_lo,
+                       m_hi, best, slot, veto);
     hipLaunchKernelGGL(clu_flag, dim3(gb), dim3(256), 0, ctx->stream, best, veto, bins, flag);
     HS_HIP(hipGetLastError());
     HS_TRY(exclusive_scan_u32(ctx, flag, bins, off, tmp));

@@ -347,7 +347,7 @@ extern "C" {
 
 const char *hs_last_error(void) { return hs::g_err; }
 
-int hs_abi_version(void) { return 9; }
+int hs_abi_version(void) { return 10; }
 
 int hs_set_mf_batch_bytes(hs_ctx *ctx, int64_t bytes) {
     HS_REQUIRE(ctx, "hs_set_mf_batch_bytes: null context");

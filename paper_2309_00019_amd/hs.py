@@ -70,7 +70,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hs_matched_filter": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
         "hs_matched_filter_noalloc": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, F, P, I64, ctypes.POINTER(I64)],
         "hs_snr_series": [P, P, I64, D, ctypes.POINTER(_Bank), P, I32, P],
-        "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
+        "hs_cluster_triggers": [P, P, I64, I64, P, I32, I64, I64, I64, I32, I64, I64, P, I64, ctypes.POINTER(I64)],
         "hs_chisq": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
         "hs_chisq_at_peaks": [P, P, I64, D, ctypes.POINTER(_Bank), P, I64, I64, I64, F, P, P, P],
         "hs_timeslide_coinc": [P, P, I64, P, I64, I32, I64, I64, I64, I64, I64, F, P, I32, P, P, I64,
@@ -345,8 +345,10 @@ def hs_snr_series(ctx: Context, spec, n: int, fs: float, bank: PreparedBank, tmp
 
 
 def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: int = 0, seg_t0: int = 0,
-                        ticks_per_sample: int = 1, cap: int = None):
-    """Returns an int32 [n_trig, 6] device tensor of hs_trigger records."""
+                        ticks_per_sample: int = 1, cap: int = None, valid=None):
+    """Returns an int32 [n_trig, 6] device tensor of hs_trigger records; valid = (m_lo, m_hi)
+    restricts the peaks to that part of the segment (default: all of it)."""
+    m_lo, m_hi = (0, n) if valid is None else (int(valid[0]), int(valid[1]))
     _dev(cand, torch.int32, "cand")
     _dev(tmpl_ids, torch.int32, "tmpl_ids")
     n_cand = cand.shape[0]
@@ -356,7 +358,7 @@ def hs_cluster_triggers(ctx: Context, cand, n: int, tmpl_ids, window: int, seg: 
         out = torch.empty((max(cap, 1), 6), dtype=torch.int32, device=cand.device)
         cnt = ctypes.c_int64(0)
         st = _lib.hs_cluster_triggers(ctx.handle, _ptr(cand), n_cand, n, _ptr(tmpl_ids), tmpl_ids.numel(), window,
-                                      seg, seg_t0, ticks_per_sample, _ptr(out), cap, ctypes.byref(cnt))
+                                      m_lo, m_hi, seg, seg_t0, ticks_per_sample, _ptr(out), cap, ctypes.byref(cnt))
         if st == HS_EOVERFLOW:
             cap = int(cnt.value)
             continue

@@ -15,7 +15,10 @@ proposer, each followed neighbourhood is cut down to the cells an MLP selects fr
 the stage-1 coincidence.
 
 Time is int64 ticks of 1/ticks_per_second s; sample m of segment s has tick
-s * seg_ticks + m * ticks_per_sample.
+s * seg_ticks + m * ticks_per_sample.  With overlapping segments of a block (pad_lo_sec /
+pad_hi_sec, Sec. V) only each segment's valid region pad_lo <= m < n - pad_hi gives triggers,
+seg_ticks is the stride n - pad_lo - pad_hi and sample m lies at s * seg_ticks + (m - pad_lo) *
+ticks_per_sample: the valid regions laid end to end are the timeline (slide ring, follow-up).
 """
 from dataclasses import dataclass, field
 
@@ -44,6 +47,11 @@ class SearchConfig:
     cluster_sec: float = 1.0      # per-slide coincidence clustering window
     coinc_min_snr: float = 0.0    # background / stage-2 coincidences below this network SNR are not formed
     stage1_min_snr: float = 0.0   # stage-1 coincidences below this are not formed (at most the follow-up bar)
+    # overlapping segments of a block (Sec. V): each segment keeps the samples pad_lo <= t < T_seg - pad_hi
+    # (its valid region); segments start every T_seg - pad_lo - pad_hi and their valid regions, laid end
+    # to end, are the timeline.  0 / 0: segments are circular and laid back to back.
+    pad_lo_sec: float = 0.0
+    pad_hi_sec: float = 0.0
     edges: tuple = tuple(round(6.0 + 0.1 * i, 1) for i in range(81))   # background count grid, 6.0 .. 14.0
     chisq_rho_min: float = 5.5    # triggers at or above this SNR get the chi-square re-weighting (None: off)
     far_x_min: float = 7.0        # Eq. (7) fit over the edges >= far_x_min with non-zero counts
@@ -102,6 +110,18 @@ def whiten_all(ctx, strains, psds, cfg: SearchConfig):
     return out
 
 
+def timeline(cfg: SearchConfig, n_full: int):
+    """(ticks per full-rate sample, pad_lo and pad_hi in full-rate samples, ticks of one segment's
+    share of the timeline): sample m (full rate) of segment s lies at tick
+    s * share + (m - pad_lo) * ticks_per_sample."""
+    tpt = int(round(cfg.ticks_per_second / cfg.fs))
+    plo = int(round(cfg.pad_lo_sec * cfg.fs))
+    phi = int(round(cfg.pad_hi_sec * cfg.fs))
+    if plo < 0 or phi < 0 or plo + phi >= n_full or plo % cfg.decim or phi % cfg.decim:
+        raise ValueError("segment pads must be non-negative multiples of the stage-1 decimation within a segment")
+    return tpt, plo, phi, (n_full - plo - phi) * tpt
+
+
 def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConfig, timer=None, with_chisq=False,
                       raw_sink=None):
     """Filter + cluster every segment of one detector; returns concatenated trigger records, and
@@ -110,7 +130,10 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
     (rho and arg z at the peak, what hs_chisq_at_peaks needs) stay intact and, with a list as
     ``raw_sink``, are appended to it (concatenated over segments)."""
     tps = int(round(cfg.ticks_per_second / fs))
-    seg_ticks = specs.shape[1] * 2 * int(round(cfg.ticks_per_second / cfg.fs))
+    n_full = specs.shape[1] * 2
+    tpt, plo, phi, share = timeline(cfg, n_full)
+    decim = n_full // n
+    valid = (plo // decim, (n_full - phi) // decim)
     window = int(round(cfg.window_sec * fs))
     parts, chis, bins, raws = [], [], [], []
     p = max(1, bank.chisq_bins)
@@ -121,11 +144,13 @@ def detector_triggers(ctx, specs, n, fs, bank, ids_per_seg, thr, cfg: SearchConf
             continue
         f = lambda: hs.hs_matched_filter(ctx, specs[s], n, fs, bank, ids, thr)
         cand = timer.run(f, n, ids, bank) if timer else f()
-        trig = hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=s * seg_ticks, ticks_per_sample=tps)
+        seg_t0 = s * share - plo * tpt
+        trig = hs.hs_cluster_triggers(ctx, cand, n, ids, window, seg=s, seg_t0=seg_t0, ticks_per_sample=tps,
+                                      valid=valid)
         if use_chisq:
             # Eq. (4): the coincidence statistic combines re-weighted SNRs
             # the triggers carry the filter's own rho and arg z: the widest bin is formed from them
-            r = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=s * seg_ticks, ticks_per_sample=tps,
+            r = hs.hs_chisq(ctx, specs[s], n, fs, bank, trig, seg_t0=seg_t0, ticks_per_sample=tps,
                             rho_min=cfg.chisq_rho_min, bins=with_chisq, at_peaks=True)
             raws.append(trig)
             trig = r[1]
@@ -193,7 +218,7 @@ def flat_search(ctx, spec_h, spec_l, fine_h, fine_l, cfg: SearchConfig, time_mf=
     rh, rl = [], []
     th = detector_triggers(ctx, spec_h, n, cfg.fs, fine_h, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rh)
     tl = detector_triggers(ctx, spec_l, n, cfg.fs, fine_l, [all_ids] * n_seg, cfg.thr2, cfg, timer, raw_sink=rl)
-    wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
+    wrap = n_seg * timeline(cfg, n)[3]
     co, bg = _coinc(ctx, th, tl, fine.n_tmpl, cfg.n_slides, cfg.step_sec, cfg, wrap, np.asarray(cfg.edges, np.float32),
                     cfg.coinc_min_snr)
     T = n / cfg.fs
@@ -216,7 +241,7 @@ def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=Non
     tl = detector_triggers(ctx, spec_l, n1, fs1, coarse_l, [c_ids] * n_seg, cfg.thr1, cfg, timer, with_chisq, rl)
     if raw is not None:
         raw.update(h1=rh[0], l1=rl[0])
-    wrap = n_seg * n * int(round(cfg.ticks_per_second / cfg.fs))
+    wrap = n_seg * timeline(cfg, n)[3]
     c1, _ = _coinc(ctx, th[0] if with_chisq else th, tl[0] if with_chisq else tl, coarse_h.n_tmpl, cfg.n_sh1,
                    cfg.t_sh1_sec, cfg, wrap, np.zeros(0, np.float32), cfg.stage1_min_snr)
     return th, tl, c1
@@ -224,8 +249,7 @@ def stage1(ctx, spec_h, spec_l, coarse_h, coarse_l, cfg: SearchConfig, timer=Non
 
 def stage1_features(ctx, th, tl, c1, coarse, n_seg: int, n: int, cfg: SearchConfig):
     """Proposer features of the stage-1 coincidences (th / tl as returned by stage1 with chisq)."""
-    tpt = int(round(cfg.ticks_per_second / cfg.fs))
-    seg_ticks = n * tpt
+    seg_ticks = timeline(cfg, n)[3]
     return hs.hs_proposer_features(ctx, c1, th[0], th[1], th[2], tl[0], tl[1], tl[2], seg_ticks, coarse.mchirp,
                                    coarse.q, int(round(cfg.t_sh1_sec * cfg.ticks_per_second)), n_seg * seg_ticks,
                                    cfg.ticks_per_second)
@@ -240,8 +264,7 @@ def hierarchical_search(ctx, spec_h, spec_l, coarse_h, coarse_l, fine_h, fine_l,
     n = spec_h.shape[1] * 2
     n_seg = spec_h.shape[0]
     timer = _MFTimer(ctx, time_mf)
-    tpt = int(round(cfg.ticks_per_second / cfg.fs))
-    seg_ticks = n * tpt
+    seg_ticks = timeline(cfg, n)[3]          # one segment's share of the timeline
     wrap = n_seg * seg_ticks
     use_p = proposer is not None
     raw = {}

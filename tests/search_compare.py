@@ -26,12 +26,15 @@ import oracle
 from oracle import coinc as _oc
 
 
-def _seg_sample(tick, seg_ticks, tps):
+def _seg_sample(tick, seg_ticks, tps, m_off=0):
+    """Segment and sample of a tick: segment s covers [s seg_ticks, (s + 1) seg_ticks) of the
+    timeline, starting at its sample m_off (the start of its valid region)."""
     s = int(tick) // seg_ticks
-    return s, (int(tick) - s * seg_ticks) // tps
+    return s, (int(tick) - s * seg_ticks) // tps + m_off
 
 
-def compare_triggers(g, o_tick, o_tmpl, o_snr_raw, thr, delta, series, window, seg_ticks, tps, only_tmpls=None):
+def compare_triggers(g, o_tick, o_tmpl, o_snr_raw, thr, delta, series, window, seg_ticks, tps, only_tmpls=None,
+                     m_off=0):
     """g: GPU trigger records (filter's own rho); o_*: the oracle's triggers (raw rho).
     series(seg, tmpl) -> the oracle's complex SNR series of that template on that segment.
     only_tmpls(seg) -> set of templates filtered on both sides (None: all).
@@ -50,7 +53,7 @@ def compare_triggers(g, o_tick, o_tmpl, o_snr_raw, thr, delta, series, window, s
     lo_band, hi_band = thr * (1 - delta), thr * (1 + delta)
     for key in set(O) ^ set(G):
         t, tick = key
-        s, m = _seg_sample(tick, seg_ticks, tps)
+        s, m = _seg_sample(tick, seg_ticks, tps, m_off)
         if only_tmpls is not None and t not in only_tmpls(s):
             diff.add(key)
             continue
@@ -184,7 +187,7 @@ def cols(rec):
 
 
 def check_stage(hs, g_raw, g_rw, o_trig, series, thr, delta, dstat, window, seg_ticks, tps, rho_min, only=None,
-                say=print):
+                say=print, m_off=0):
     """Triggers of both detectors under the tolerance rule, and the re-weighted rho of the common
     ones within dstat / 2.  g_raw / g_rw: (H, L) GPU trigger tensors before / after re-weighting;
     o_trig: the oracle's (H, L) trigger columns (with snr_raw); series: (H, L) series functions.
@@ -195,7 +198,7 @@ def check_stage(hs, g_raw, g_rw, o_trig, series, thr, delta, dstat, window, seg_
         gr = hs.as_records(g_rw[det], hs.TRIGGER)
         o = o_trig[det]
         diff, common = compare_triggers(g, o["tick"], o["tmpl"], o["snr_raw"], thr, delta, series[det], window,
-                                        seg_ticks, tps, only)
+                                        seg_ticks, tps, only, m_off)
         assert np.array_equal(g["tick"], gr["tick"]) and np.array_equal(g["tmpl"], gr["tmpl"])
         near_cut = {(int(a), int(b)) for a, b, r in zip(g["tmpl"], g["tick"], g["snr"])
                     if abs(r / rho_min - 1.0) <= delta}

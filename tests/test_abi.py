@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_abi_version_and_error_string_without_gpu():
     from paper_2309_00019_amd import hs
     lib = hs.load_library()
-    assert lib.hs_abi_version() == 9
+    assert lib.hs_abi_version() == 10
     assert isinstance(lib.hs_last_error(), bytes)
 
 
