@@ -65,6 +65,11 @@ def parse():
                     help="restrict the run (profiling): hier = hierarchical + proposer only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="only the batched uneven-length filtering workload (64 segments x 20,000 templates, "
+                         "chirp mass 1.2-10) in FP32, BF16 and FP16 template storage")
+    ap.add_argument("--batched-segments", type=int, default=64)
+    ap.add_argument("--batched-templates", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -161,7 +166,7 @@ def host_description():
     return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None):
+def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None, all_cores=True):
     """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores):
     one core in this process, then every usable core (at most 16, the machine's CPU share) as a
     pool of spawned processes each running the unchanged oracle on its share of the templates.
@@ -178,23 +183,25 @@ def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None):
     done, t_used = _oracle_filter_share((st, psd, n, fs, f_low, m1[order], m2[order], args.cpu_seconds))
     T = n / fs
     host = host_description()
-    workers = max(1, min(16, host["usable_cpus"] or 1))
+    workers = max(1, min(16, host["usable_cpus"] or 1)) if all_cores else 0
     rest = order[done:]
     shares = [rest[w::workers] for w in range(workers)]
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(workers) as pool:
-        got = pool.map(_oracle_filter_share, [(st, psd, n, fs, f_low, m1[sh], m2[sh], args.cpu_seconds)
-                                              for sh in shares])
+    got = [(0, 1.0)]
+    if workers:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            got = pool.map(_oracle_filter_share, [(st, psd, n, fs, f_low, m1[sh], m2[sh], args.cpu_seconds)
+                                                  for sh in shares])
     wall = time.perf_counter() - t0
     done_all = sum(d for d, _ in got)
     busy = max(t for _, t in got)
     base = {"value": done * T / t_used, "unit": "template-s/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} fine templates x 1 detector x {T:.0f} s at {fs:.0f} Hz: FP64 matched filter "
                       f"+ threshold (numpy FFT, one thread), {t_used:.1f} s",
-            "all_cores": {"value": done_all * T / busy, "unit": "template-s/s", "cores": workers,
-                          "sample": f"{done_all} further fine templates of the same sample split over {workers} "
-                                    f"processes (one thread each), {busy:.1f} s of filtering per process "
-                                    f"({wall:.1f} s wall with process start-up)"},
+            "all_cores": ({"value": done_all * T / busy, "unit": "template-s/s", "cores": workers,
+                           "sample": f"{done_all} further fine templates of the same sample split over {workers} "
+                                     f"processes (one thread each), {busy:.1f} s of filtering per process "
+                                     f"({wall:.1f} s wall with process start-up)"} if workers else None),
             "host": host}
     if ctx is None:
         return base, None
@@ -224,6 +231,79 @@ def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None):
     return base, err
 
 
+def batched_filtering(args):
+    """Batched uneven-length filtering: 64 segments of 256 s at 2048 Hz (one detector, noise and
+    glitches, seed family 3) against 20,000 templates with chirp mass 1.2-10 and q 1-4, uniform in
+    tau0 (durations ~4.7-160 s from 20 Hz, bands of ~33 k to 257 k bins), in each template storage
+    (FP32, BF16, FP16; FP32 transforms and accumulation).  Per storage: the schedule measured on
+    every 10th template, then one pass over all segments (filter, threshold, clustering, chi-square
+    at the peaks) timed with its matched-filter launches event-timed, the filter's roofline, and the
+    SNR error against the FP64 oracle on a sample (the CPU-baseline leg).  Prints one JSON line."""
+    import multiprocessing as mp
+    import torch
+    import synth
+    from paper_2309_00019_amd import autotune, hs, search, workload
+    fs, f_low = workload.FS, workload.F_LOW
+    n = int(256 * fs)
+    n_seg, n_t = args.batched_segments, args.batched_templates
+    ctx = hs.Context(0)
+    dev = ctx.device
+    m1, m2 = synth.bank_by_tau0(n_t, 1.2, 10.0, 1.0, 4.0, synth.rng(3, 0, 0, synth.BANK))
+    jobs = [(r, 0, 3, n, fs, f_low, (1.2, 10.0), (1.0, 4.0), workload.GLITCH_RATE) for r in range(n_seg)]
+    if n_seg <= 16:                 # a few segments: in this process (also what a profiler run wants)
+        strains = [synth.realisation_job(j)[1][0] for j in jobs]
+    else:
+        with mp.get_context("spawn").Pool(16, initializer=synth.single_threaded) as pool:
+            strains = [sh for _, (sh, _, _) in sorted(pool.map(synth.realisation_job, jobs, chunksize=2),
+                                                     key=lambda x: x[0])]
+    L = int(4 * fs)
+    psd = hs.hs_welch_psd(ctx, torch.as_tensor(strains[0], device=dev), fs, L)
+    specs = torch.stack([hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, psd) for x in strains])
+    cfg = search.SearchConfig(fs=fs, f_low=f_low)
+    ids = torch.arange(n_t, dtype=torch.int32, device=dev)
+    from synth.bank import bank_layout
+    k0, kstart, k1, _, _ = bank_layout(m1, m2, n, fs, f_low)
+    dur = synth.bank.tau0(synth.mchirp_eta(m1, m2)[0], f_low)
+    T = n / fs
+    out = {"metric": "template-seconds filtered/s on 1 GPU, batched uneven-length filtering", "unit": "template-s/s",
+           "config": {"workload": f"{n_seg} segments x 256 s at 2048 Hz (one detector, noise + glitches 0.05/s), "
+                                  f"{n_t} templates, chirp mass 1.2-10, q 1-4, uniform in tau0",
+                      "template_duration_s": [round(float(dur.min()), 1), round(float(dur.max()), 1)],
+                      "band_bins": [int((k1 - kstart).min()), int((k1 - kstart).max())]}}
+    for dtype in ("f32", "bf16", "f16"):
+        bank, = workload.make_banks(ctx, n, fs, f_low, m1, m2, [psd], dtype, args.chunk)
+        sched = autotune.tune_mf_schedule(ctx, specs[0], n, fs, bank, ids[::10].contiguous(), cfg.thr2)
+        search.detector_triggers(ctx, specs[:1], n, fs, bank, [ids], cfg.thr2, cfg)     # warm-up
+        torch.cuda.synchronize()
+        timer = search._MFTimer(ctx, True)
+        t0 = time.perf_counter()
+        trig = search.detector_triggers(ctx, specs, n, fs, bank, [ids] * n_seg, cfg.thr2, cfg, timer)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        mf_b = mf_bytes(timer.units, hs)
+        per = hs.mf_batch_templates(n, n_t, ctx)
+        launches = n_seg * (-(-n_t // per))
+        achieved = mf_b / (timer.ms * 1e-3) / 1e9
+        err = None
+        if not args.no_cpu:
+            args_d = argparse.Namespace(**{**vars(args), "dtype": dtype, "cpu_seconds": 2.0})
+            _, err = cpu_baseline(args_d, synth, n, fs, f_low, strains[0], m1, m2, ctx, all_cores=False)
+        out[dtype] = {"template_s_per_s": round(n_seg * n_t * T / wall, 1), "wall_s": round(wall, 3),
+                      "mf_us_per_template": round(timer.ms * 1e3 / (n_seg * n_t), 4),
+                      "triggers": int(trig.shape[0]),
+                      "schedule": {k: sched[k] for k in ("batch_mb", "tile", "pa_cols")},
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "per_launch_ms": round(timer.ms / launches, 4), "templates_per_launch": per,
+                                   "bytes_per_launch": int(mf_b / launches)},
+                      "snr_error_vs_fp64": err}
+        log(f"[batched] {dtype}: {json.dumps(out[dtype])}")
+        del bank, trig
+        torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,6 +315,9 @@ def main():
     from paper_2309_00019_amd import autotune, hs, search, workload
     from paper_2309_00019_amd.proposer import Proposer
 
+    if args.batched:
+        batched_filtering(args)
+        return
     if args.calib_copy:
         # reference kernels of known size: a 1 GiB device copy (calibrates the HBM byte
         # counters) and the achievable bandwidth of copy and write-only fill
@@ -294,6 +377,11 @@ def main():
                  "pa_tiles": {}}
     else:
         sched = autotune.tune_mf_schedule(ctx, spec_tune, n, fs, fine_h, tune_ids, cfg.thr2)
+        # stage 1 has its own length (n / 4) and bank: its schedule is measured separately, on the
+        # leading quarter of the same whitened spectrum and every coarse template
+        sched["stage1"] = autotune.tune_mf_schedule(
+            ctx, spec_tune[: n1 // 2].contiguous(), n1, fs1, coarse_h,
+            torch.arange(args.coarse, dtype=torch.int32, device=dev), cfg.thr1)
     best_mb, tune_table = sched["batch_mb"], sched["budgets"]
     del spec_tune
     torch.cuda.synchronize()
@@ -455,6 +543,10 @@ def main():
                    "mf_batch_mb": best_mb, "mf_autotune_us_per_template": tune_table,
                    "mf_tile_threads": sched["tile"], "mf_autotune_tile_us_per_template": sched["tiles"],
                    "mf_pass_a_columns": sched["pa_cols"], "mf_autotune_pass_a_us_per_template": sched["pa_tiles"],
+                   "mf_stage1_schedule": ({k: sched["stage1"][k] for k in ("batch_mb", "tile", "pa_cols")}
+                                          if "stage1" in sched else None),
+                   "mf_stage1_autotune_us_per_template": ({k: sched["stage1"][k] for k in ("budgets", "tiles", "pa_tiles")}
+                                                          if "stage1" in sched else None),
                    "raw_template_seconds_per_s": round(raw_ts / wall_m, 1)},
         "roofline": roof,
     }

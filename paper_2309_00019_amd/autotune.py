@@ -6,7 +6,7 @@ ramp and tail more often; larger ones than the best have also measured slower.  
 rows of the intermediate one workgroup transforms) trades LDS per workgroup against the number
 of workgroups; pass A's tile (the columns one workgroup transforms) sets the width of the
 pieces in which each row of the intermediate is written.  The best setting depends on N, the
-bank's band lengths and the candidate volume, so it is measured: the filter runs on a sample of
+bank's band lengths and the candidate volume, so it is measured per transform length: the filter runs on a sample of
 the real bank and data for each candidate (device time from events on the library's stream),
 first over the batch budgets at the default tiles, then over the pass-B tiles at the best budget,
 then over the pass-A tiles, and the fastest is set on the context.  No knob changes the results
@@ -52,7 +52,9 @@ def tune_mf_schedule(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, t
                      tiles=TILES, pa_cols=PA_COLS, reps: int = 3):
     """Batch budget, then pass-B tile, then pass-A tile; sets all three on ctx and returns
     {"batch_mb", "tile", "pa_cols", "budgets": {mb: us/template}, "tiles": {threads: us/template},
-    "pa_tiles": {columns: us/template}}."""
+    "pa_tiles": {columns: us/template}}; the result is also recorded as the context's schedule for
+    length n (hs.apply_mf_schedule sets it before every filter call at that n)."""
+    ctx.mf_schedules.pop(int(n), None)
     hs.hs_set_mf_tile(ctx, 128)
     hs.hs_set_mf_pa_cols(ctx, 64)
     best_mb, budgets = tune_mf_batch(ctx, spec, n, fs, bank, tmpl_ids, thr, budgets_mb, reps)
@@ -68,5 +70,6 @@ def tune_mf_schedule(ctx: hs.Context, spec, n: int, fs: float, bank, tmpl_ids, t
         pa_table[int(c)] = table[best_t] if c == 64 else _time(ctx, spec, n, fs, bank, tmpl_ids, thr, reps)
     best_c = min(pa_table, key=pa_table.get)
     hs.hs_set_mf_pa_cols(ctx, best_c)
+    ctx.mf_schedules[int(n)] = (best_mb << 20, best_t, best_c)
     return {"batch_mb": best_mb, "tile": best_t, "pa_cols": best_c, "budgets": budgets, "tiles": table,
             "pa_tiles": pa_table}

@@ -137,6 +137,11 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.hs_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream)), "hs_create")
         self.handle = h
+        # matched-filter schedule per transform length n: (batch bytes, pass-B threads, pass-A
+        # columns), applied before each filter call at that n (the autotuner fills it)
+        self.mf_schedules = {}
+        # largest candidate fraction (x 1.25) seen per threshold: sizes later candidate buffers
+        self.cand_fraction = {}
 
     def close(self):
         if getattr(self, "handle", None):
@@ -190,7 +195,8 @@ class PreparedBank:
 def mf_batch_templates(n: int, n_ids: int, ctx: "Context" = None) -> int:
     """Templates per pass-A/pass-B launch in hs_matched_filter (same rule as the library)."""
     if ctx is not None:
-        budget = hs_get_mf_batch_bytes(ctx)
+        sch = ctx.mf_schedules.get(int(n))
+        budget = sch[0] if sch is not None else hs_get_mf_batch_bytes(ctx)
     else:
         try:
             mb = int(os.environ.get("HS_MF_BATCH_MB", "0") or 0)
@@ -198,6 +204,20 @@ def mf_batch_templates(n: int, n_ids: int, ctx: "Context" = None) -> int:
             mb = 0
         budget = (mb << 20) if 1 <= mb <= (1 << 16) else (128 << 20)
     return max(1, min(65535, n_ids, budget // (n * 8)))
+
+
+def apply_mf_schedule(ctx: "Context", n: int):
+    """Sets the context's matched-filter schedule for length n, when one was recorded for it."""
+    sch = ctx.mf_schedules.get(int(n))
+    if sch is None:
+        return
+    b, t, c = sch
+    if _lib.hs_get_mf_batch_bytes(ctx.handle) != b:
+        _check(_lib.hs_set_mf_batch_bytes(ctx.handle, int(b)), "hs_set_mf_batch_bytes")
+    if _lib.hs_get_mf_tile(ctx.handle) != t:
+        _check(_lib.hs_set_mf_tile(ctx.handle, int(t)), "hs_set_mf_tile")
+    if _lib.hs_get_mf_pa_cols(ctx.handle) != c:
+        _check(_lib.hs_set_mf_pa_cols(ctx.handle, int(c)), "hs_set_mf_pa_cols")
 
 
 def hs_set_mf_batch_bytes(ctx: "Context", nbytes: int):
@@ -289,10 +309,15 @@ def hs_matched_filter(ctx: Context, spec, n: int, fs: float, bank: PreparedBank,
     """Returns an int32 [n_cand, 4] device tensor of hs_candidate records (view with as_records)."""
     _dev(spec, torch.complex64, "spec")
     _dev(tmpl_ids, torch.int32, "tmpl_ids")
+    apply_mf_schedule(ctx, n)
     n_ids = tmpl_ids.numel()
     if cap is None:
-        # Rayleigh tail e^{-thr^2/2} per sample, with head-room for loud glitches
-        cap = int(n_ids * n * min(1.0, 8.0 * np.exp(-thr * thr / 2.0))) + 65536
+        # Rayleigh tail e^{-thr^2/2} per sample, with head-room for loud glitches; a glitch that rings
+        # every template can exceed it, which costs a second pass, so the context remembers the
+        # largest fraction of candidates per (template, sample) seen at this threshold
+        frac = min(1.0, 8.0 * np.exp(-thr * thr / 2.0))
+        frac = max(frac, ctx.cand_fraction.get(float(thr), 0.0))
+        cap = int(n_ids * n * frac) + 65536
     bs = bank.struct()
     for _ in range(2):
         if cand is None or cand.shape[0] < cap:
@@ -300,6 +325,10 @@ def hs_matched_filter(ctx: Context, spec, n: int, fs: float, bank: PreparedBank,
         cnt = ctypes.c_int64(0)
         st = _lib.hs_matched_filter(ctx.handle, _ptr(spec), n, fs, ctypes.byref(bs), _ptr(tmpl_ids), n_ids,
                                     float(thr), _ptr(cand), cand.shape[0], ctypes.byref(cnt))
+        if n_ids:
+            seen = 1.25 * cnt.value / (n_ids * n)
+            if seen > ctx.cand_fraction.get(float(thr), 0.0):
+                ctx.cand_fraction[float(thr)] = min(1.0, seen)
         if st == HS_EOVERFLOW:
             cap = int(cnt.value)
             cand = None
