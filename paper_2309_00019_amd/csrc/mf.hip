@@ -122,20 +122,29 @@ __global__ __launch_bounds__(16 * COLS, 64 / COLS) void mf_pass_a(
     const int lo = it.lo, hi = it.hi;
 
     // All 32 band loads are issued before any product uses them: a use right after each
-    // band-tested load would make the wavefront wait for every row in turn.
-    float2 dd[16], tt[16], x[16];
+    // band-tested load would make the wavefront wait for every row in turn.  The stored template
+    // elements are kept raw inside the band tests and unpacked after them (an unpack inside a
+    // test would wait there for its load).
+    float2 dd[16], x[16];
+    typename ST::elem te[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int k = k1 + N1 * (l + 16 * j);
         dd[j] = float2{0.0f, 0.0f};
-        tt[j] = float2{0.0f, 0.0f};
+        te[j] = ST::zero();
         if (k >= lo && k <= hi) {
             dd[j] = dspec[k];
-            tt[j] = ST::load(spectra, base + k);
+            te[j] = spectra[base + k];
         }
     }
+    if constexpr (ST::bytes == 4) {
+        // An empty asm that takes each raw element as an operand pins it after the load loop, so
+        // the compiler cannot fold the conversion into the band test (where it would wait).
 #pragma unroll
-    for (int j = 0; j < 16; ++j) x[j] = cmulc(dd[j], tt[j]);
+        for (int j = 0; j < 16; ++j) asm volatile("" : "+v"(te[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = cmulc(dd[j], ST::unpack(te[j]));
     float2 *Yt = Y + (size_t)tb * 512 * (size_t)N1;
     // Twiddles: W_512^{k2} = W_512^l W_32^j; the W_32^j are compile-time constants applied
     // before the radix-16 DFT over j, and the common factor W_512^l is merged after it with
