@@ -233,13 +233,16 @@ __host__ __device__ constexpr int pass_out_index(int ln, int e) {
 
 // Placement of row element i in LDS.  The first pass writes 16 consecutive elements per lane
 // (a 128-byte lane stride), which unmapped puts the lanes of a wavefront on the same banks.
-// The LDS serves 8-byte accesses 32 lanes per cycle over 64 four-byte banks, so an access is
-// conflict-free when its 32 lanes hit distinct (element mod 32) slots.  Rows of >= 512
-// elements use an XOR swizzle of the low five bits (no padding) and shorter rows one pad
-// element per 16; both were checked conflict-free for every pass of every plan with a model
-// of that bank mapping.
+// Measured on gfx950 (SQ_LDS_BANK_CONFLICT of single-pattern probes): an 8-byte read is served
+// 32 lanes at a time and is conflict-free when those lanes hit distinct (element mod 32)
+// slots; an 8-byte write is served 16 consecutive lanes at a time and is conflict-free when
+// they hit distinct (element mod 16) slots.  Rows of >= 512 elements XOR bits 4-7 of the
+// index into bits 0-3 (no padding): the first pass's 16 lanes then write 16 distinct slots,
+// and every other access still reads or writes whole 16-element blocks.  Shorter rows take
+// one pad element per 16.  Both were checked conflict-free for every pass of every plan and
+// tile with a model of those rules.
 template <int N1> __host__ __device__ constexpr int lds_map(int i) {
-    if constexpr (N1 >= 512) return i ^ (((i >> 5) ^ ((i >> 8) << 4)) & 31);
+    if constexpr (N1 >= 512) return i ^ ((i >> 4) & 15);
     else return i + (i >> 4);
 }
 template <int N1> constexpr int lds_row_len() { return N1 >= 512 ? N1 : N1 + N1 / 16; }
