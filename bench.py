@@ -78,7 +78,7 @@ def mf_bytes(units, hs):
     spectrum (element bytes) and of whitened data (8 B) read once, plus the N-point complex64
     intermediate written by pass A and read by pass B (16 N bytes)."""
     total = 0
-    for n, ids, bank in units:
+    for n, ids, bank, *_ in units:
         kl = bank.k_lo[ids.long()].to(dtype=__import__("torch").int64)
         kh = bank.k_hi[ids.long()].to(dtype=__import__("torch").int64)
         K = int((kh - kl + 1).sum().item())
@@ -508,17 +508,31 @@ def main():
     # flat pass (the calls of the hierarchical pass when the flat search is skipped)
     src = flat["res_t"] if flat else res_mt
     mf_b = mf_bytes(src.mf_units, hs)
-    launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel(), ctx)) for n_, ids, _ in src.mf_units)
+    launches = sum(-(-ids.numel() // hs.mf_batch_templates(n_, ids.numel(), ctx)) for n_, ids, *_ in src.mf_units)
     achieved = mf_b / (src.mf_ms * 1e-3) / 1e9
     # the counters were taken on the default workload (fine bank at 2^19 samples, float32 storage)
     per_tmpl = measured_traffic_per_template() if (n == 2 ** 19 and args.dtype == "f32") else None
-    n_tmpl_mf = sum(ids.numel() for _, ids, _ in src.mf_units)
+    n_tmpl_mf = sum(ids.numel() for _, ids, *_ in src.mf_units)
     traffic = None if per_tmpl is None else int(per_tmpl * n_tmpl_mf / max(1, launches))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "matched filter: mf_pass_a + mf_pass_b over one template batch",
             "per_launch_ms": round(src.mf_ms / max(1, launches), 4), "launches": launches,
             "bytes_per_launch": int(mf_b / max(1, launches))}
+    # the same per transform length over the event-timed hierarchy + proposer pass: stage 1
+    # (coarse bank, 512 Hz) and stage 2 (followed fine templates, 2048 Hz)
+    by_n = {}
+    for unit in res_mt.mf_units:
+        by_n.setdefault(unit[0], []).append(unit)
+    roof["hier_mlp_by_transform_length"] = {}
+    for n_, units in sorted(by_n.items()):
+        b_ = mf_bytes(units, hs)
+        ms_ = sum(u[3] for u in units)
+        l_ = sum(-(-u[1].numel() // hs.mf_batch_templates(n_, u[1].numel(), ctx)) for u in units)
+        a_ = b_ / (ms_ * 1e-3) / 1e9
+        roof["hier_mlp_by_transform_length"]["2^%d" % (n_.bit_length() - 1)] = {
+            "achieved": round(a_, 1), "frac": round(a_ / HBM_PEAK_GBS, 4), "device_ms": round(ms_, 3),
+            "templates": int(sum(u[1].numel() for u in units)), "launches": l_}
     out = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -73,7 +73,7 @@ class SearchResult:
     followed: list = field(default_factory=list)
     mf_ms: float = 0.0                   # device time inside matched-filter calls (events)
     mf_calls: int = 0
-    mf_units: list = field(default_factory=list)   # (n, ids, bank) per matched-filter call
+    mf_units: list = field(default_factory=list)   # (n, ids, bank, device ms) per matched-filter call
     far: dict = None                                # background_far() output, when computed
     fine_ids: list = None                           # per segment: followed fine template ids (device)
     raw: dict = None                                # the filter's own triggers before re-weighting:
@@ -95,9 +95,10 @@ class _MFTimer:
         out = fn()
         e.record(self.ctx.stream)
         e.synchronize()
-        self.ms += s.elapsed_time(e)
+        ms = s.elapsed_time(e)
+        self.ms += ms
         self.calls += 1
-        self.units.append((n, ids, bank))
+        self.units.append((n, ids, bank, ms))
         return out
 
 
