@@ -146,7 +146,8 @@ int hs_welch_psd(hs_ctx *ctx, const float *strain, int64_t n, double fs, int64_t
 /*
  * Whitened data spectrum d~[k] = x~[k] / sqrt(S[k]) for k_lo <= k <= n/2 - 1,
  * zero for k < k_lo; k_lo = max(1, ceil(f_low n / fs)) (lower limit of Eq. (2)).
- * The transform runs in float32; the division in float64.
+ * The transform is real-input: an n/2-point complex transform in float32 of the
+ * sample pairs, recombined and divided in float64.
  *   strain   device float  [n]          n a power of two, 2^10 <= n <= 2^22
  *   psd      device double [n/2 + 1]    positive and finite on the band (not
  *            checked here: the call does not synchronise; hs_prepare_bank checks it)

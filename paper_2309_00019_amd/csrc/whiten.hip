@@ -61,25 +61,35 @@ __global__ __launch_bounds__(256) void welch_interp(const double *__restrict__ p
     psd[k] = __dadd_rn(__dmul_rn(slope, __dsub_rn(fk, fj)), pw[j]);
 }
 
-__global__ __launch_bounds__(256) void real_to_complex(const float *__restrict__ s, int64_t n,
-                                                       float2 *__restrict__ out) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = float2{s[i], 0.0f};
+// The real series as n/2 complex samples z[j] = s[2j] + i s[2j+1] (the transform of a real
+// series of length n from one of length n/2).
+__global__ __launch_bounds__(256) void pack_pairs(const float *__restrict__ s, int64_t h, float2 *__restrict__ z) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < h) z[j] = float2{s[2 * j], s[2 * j + 1]};
 }
 
-// d~[k] = dt * X[k] / sqrt(S[k]) for k_lo <= k < n/2, 0 below k_lo.
-__global__ __launch_bounds__(256) void whiten_scale(const float2 *__restrict__ X, int64_t n, int64_t k_lo,
-                                                    double dt, const double *__restrict__ psd,
-                                                    float2 *__restrict__ out) {
+// With Z the n/2-point transform of z, the even and odd samples' transforms are
+// E_k = (Z_k + conj Z_{n/2-k}) / 2 and O_k = (Z_k - conj Z_{n/2-k}) / (2i) (Z_{n/2} = Z_0), and
+// the series' transform is X_k = E_k + exp(-2 pi i k / n) O_k.  Then d~[k] = dt X[k] / sqrt(S[k])
+// for k_lo <= k < n/2, 0 below k_lo; the recombination runs in float64 (exact sincospi of k / n).
+__global__ __launch_bounds__(256) void whiten_r2c(const float2 *__restrict__ Z, int64_t n, int64_t k_lo,
+                                                  double dt, const double *__restrict__ psd,
+                                                  float2 *__restrict__ out) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n / 2) return;
+    const int64_t h = n / 2;
+    if (k >= h) return;
     if (k < k_lo) {
         out[k] = float2{0.0f, 0.0f};
         return;
     }
+    const float2 a = Z[k], b = Z[(h - k) & (h - 1)];
+    const double er = 0.5 * ((double)a.x + (double)b.x), ei = 0.5 * ((double)a.y - (double)b.y);
+    const double orr = 0.5 * ((double)a.y + (double)b.y), oi = -0.5 * ((double)a.x - (double)b.x);
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)n, &sn, &cs);  // exp(-2 pi i k / n) = cs - i sn
+    const double xr = er + (cs * orr + sn * oi), xi = ei + (cs * oi - sn * orr);
     const double g = dt / sqrt(psd[k]);
-    const float2 v = X[k];
-    out[k] = float2{(float)((double)v.x * g), (float)((double)v.y * g)};
+    out[k] = float2{(float)(xr * g), (float)(xi * g)};
 }
 
 }  // namespace hs
@@ -131,16 +141,18 @@ int hs_whiten(hs_ctx *ctx, const float *strain, int64_t n, double fs, double f_l
     HS_HIP(hipSetDevice(ctx->device));
     int64_t k_lo = (int64_t)std::ceil(f_low * (double)n / fs);
     if (k_lo < 1) k_lo = 1;
+    // real-input transform: an n/2-point complex transform of the sample pairs, recombined
+    const int64_t h = n / 2;
     float2 *a, *b;
     Carver cv;
-    cv.add(&a, n);
-    cv.add(&b, n);
+    cv.add(&a, h);
+    cv.add(&b, h);
     HS_TRY(cv.commit(ctx));
-    hipLaunchKernelGGL(real_to_complex, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, ctx->stream, strain, n, a);
+    hipLaunchKernelGGL(pack_pairs, dim3((unsigned)cdiv(h, 256)), dim3(256), 0, ctx->stream, strain, h, a);
     HS_HIP(hipGetLastError());
-    float2 *X;
-    HS_TRY(fft_c2c_f32(ctx, a, b, ilog2(n), 1, -1, &X));
-    hipLaunchKernelGGL(whiten_scale, dim3((unsigned)cdiv(n / 2, 256)), dim3(256), 0, ctx->stream, X, n, k_lo,
+    float2 *Z;
+    HS_TRY(fft_c2c_f32(ctx, a, b, ilog2(h), 1, -1, &Z));
+    hipLaunchKernelGGL(whiten_r2c, dim3((unsigned)cdiv(h, 256)), dim3(256), 0, ctx->stream, Z, n, k_lo,
                        1.0 / fs, psd, static_cast<float2 *>(spec_out));
     HS_HIP(hipGetLastError());
     return HS_OK;
