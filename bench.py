@@ -166,10 +166,13 @@ def host_description():
     return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None, all_cores=True):
+def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None, all_cores=True, strain_l=None, cfg=None):
     """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores):
     one core in this process, then every usable core (at most 16, the machine's CPU share) as a
     pool of spawned processes each running the unchanged oracle on its share of the templates.
+    With the L strain and the search configuration it also times the oracle's whole flat
+    pipeline (both detectors: filter, clustering, chi-square re-weighting, coincidence over the
+    slides, background counts) on a sample of templates sized to the same budget.
 
     With a context it also returns the SNR error of the GPU path against that FP64 filter on the
     sample's first templates (same data and PSD on both sides): (baseline dict, error dict)."""
@@ -203,6 +206,26 @@ def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None, all_core
                                      f"processes (one thread each), {busy:.1f} s of filtering per process "
                                      f"({wall:.1f} s wall with process start-up)"} if workers else None),
             "host": host}
+    if strain_l is not None and cfg is not None and done:
+        # whole flat pipeline on K templates: about the budget at ~6 filter times per template
+        # (two detectors, each ~3 filter times with clustering, chi-square and coincidence)
+        per_filter = t_used / done
+        K = max(2, int(args.cpu_seconds / (6.0 * per_filter)))
+        take = order[done:done + K] if done + K <= len(order) else order[:K]
+        b = synth.taylorf2_bank(m1[take], m2[take], n, fs, f_low)
+        psd_l = oracle.psd_on_grid(oracle.welch_psd(strain_l.astype(np.float64), fs, L), fs, L, n)
+        t1 = time.perf_counter()
+        res = oracle.flat_search([strain_h], [strain_l], [psd], [psd_l], fs, f_low, b, thr=cfg.thr2,
+                                 window_sec=cfg.window_sec, ticks_per_second=cfg.ticks_per_second,
+                                 n_slides=cfg.n_slides, step_sec=cfg.step_sec, coinc_window_sec=cfg.coinc_window_sec,
+                                 cluster_sec=cfg.cluster_sec, edges=cfg.edges, chisq_bins=8,
+                                 chisq_rho_min=cfg.chisq_rho_min)
+        t_p = time.perf_counter() - t1
+        base["pipeline"] = {"value": 2 * K * T / t_p, "unit": "template-s/s", "cores": 1,
+                            "sample": f"{K} fine templates x 2 detectors x {T:.0f} s: the oracle's flat search (FP64 "
+                                      f"filter, clustering, chi-square re-weighting, coincidence over {cfg.n_slides} "
+                                      f"slides, background counts; {len(res['trig_h']['tick'])} + "
+                                      f"{len(res['trig_l']['tick'])} triggers), one thread, {t_p:.1f} s"}
     if ctx is None:
         return base, None
     import torch
@@ -617,7 +640,7 @@ def main():
     if not args.no_cpu:
         log("[cpu] timing the oracle on a bounded sample")
         out["cpu_baseline"], out["snr_error_vs_fp64"] = cpu_baseline(args, synth, n, fs, f_low, strains[0], fm1,
-                                                                     fm2, ctx)
+                                                                     fm2, ctx, strain_l=strains[1], cfg=cfg)
     ctx.close()
     print(json.dumps(out), flush=True)
 
