@@ -272,7 +272,7 @@ def batched_filtering(args):
     ctx = hs.Context(0)
     dev = ctx.device
     m1, m2 = synth.bank_by_tau0(n_t, 1.2, 10.0, 1.0, 4.0, synth.rng(3, 0, 0, synth.BANK))
-    jobs = [(r, 0, 3, n, fs, f_low, (1.2, 10.0), (1.0, 4.0), workload.GLITCH_RATE) for r in range(n_seg)]
+    jobs = list(workload.realisation_jobs(range(n_seg), 0, n, cfg=3, mc_range=(1.2, 10.0), q_range=(1.0, 4.0)))
     if n_seg <= 16:                 # a few segments: in this process (also what a profiler run wants)
         strains = [synth.realisation_job(j)[1][0] for j in jobs]
     else:
@@ -483,8 +483,7 @@ def main():
             if thr is None:
                 return np.zeros(len(t_inj), bool)
             return found_injections(hs.as_records(res.coincs, hs.COINC), t_inj, int(0.1 * tick), thr)
-        jobs = [(args.inj_seed0 + r, per_seg, workload.CFG, n, fs, f_low, workload.MC_RANGE, workload.Q_RANGE,
-                 workload.GLITCH_RATE) for r in range(count)]
+        jobs = workload.realisation_jobs(range(args.inj_seed0, args.inj_seed0 + count), per_seg, n)
         with mp.get_context("spawn").Pool(16, initializer=synth.single_threaded) as pool:
             for i, (r, (sh_, sl_, ip)) in enumerate(pool.imap(synth.realisation_job, jobs, chunksize=2)):
                 specs = [hs.hs_whiten(ctx, torch.as_tensor(x, device=dev), fs, f_low, p)[None]

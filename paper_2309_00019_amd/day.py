@@ -43,13 +43,20 @@ def _segment_job(args):
 
 
 def injections_of_day(n_seg, n, fs, mc_range, q_range, margin=8.0):
-    """One injection per segment (parameters from the segment's own injection stream)."""
+    """One injection per segment (parameters from the segment's own injection stream), with the
+    amplitude factors of its H and L SNRs."""
     import synth
+    from . import workload
     out = []
     for s in range(n_seg):
         ip = synth.injection_params(1, synth.rng(CFG, 0, s, synth.INJECT), mc_range[0], mc_range[1], q_range[0],
                                     q_range[1], n / fs, margin=margin)
         out.append({k: float(v[0]) for k, v in ip.items()})
+    amp_h = workload.injection_amplitudes([p["m1"] for p in out], [p["m2"] for p in out],
+                                          [p["snr_h"] for p in out], n, fs)
+    for p, a in zip(out, amp_h):
+        p["amp_h"] = float(a)
+        p["amp_l"] = float(a * p["snr_l"] / p["snr_h"])
     return out
 
 
@@ -65,7 +72,7 @@ def whitened_day(ctx, pool, n_seg, n, fs, f_low, glitch, psds, injections=None):
             inj = None
             if injections is not None:
                 p = injections[s]
-                inj = dict(m1=p["m1"], m2=p["m2"], t_c=p["tc_" + key], phi_c=p["phi_" + key], snr=p["snr_" + key])
+                inj = dict(m1=p["m1"], m2=p["m2"], t_c=p["tc_" + key], phi_c=p["phi_" + key], amp=p["amp_" + key])
             jobs.append((det, s, n, fs, f_low, glitch, inj))
     done = 0
     for det, s, x in pool.imap_unordered(_segment_job, jobs, chunksize=4):

@@ -40,8 +40,7 @@ def collect(ctx, pool, rs, per_seg, coarse_h, coarse_l, psd_h, psd_l, cfg, label
     n_inj = 0
     t0 = time.perf_counter()
     t_gpu = 0.0
-    jobs = [(r, per_seg, workload.CFG, N_SAMPLES, workload.FS, workload.F_LOW, workload.MC_RANGE, workload.Q_RANGE,
-             workload.GLITCH_RATE) for r in rs]
+    jobs = workload.realisation_jobs(rs, per_seg, N_SAMPLES)
     for k, (r, (sh, sl, ip)) in enumerate(pool.imap(synth.realisation_job, jobs, chunksize=2)):
         tg = time.perf_counter()
         spec_h = hs.hs_whiten(ctx, torch.as_tensor(sh, device=dev), workload.FS, workload.F_LOW, psd_h)[None]

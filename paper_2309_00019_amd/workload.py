@@ -56,8 +56,38 @@ def background_strains(n: int):
     return [synth.make_strain(CFG, det, 0, n, FS, F_LOW, glitch_rate=GLITCH_RATE)[0] for det in (0, 1)]
 
 
+def injection_amplitudes(m1, m2, snr, n: int, fs: float = FS, f_low: float = F_LOW, chunk: int = 256):
+    """Loudness of the synthetic injections: the factor on synth's TaylorF2 spectrum of each pair
+    (m1, m2) that makes its optimal SNR ``snr`` in the analytic PSD of the synthetic noise,
+    snr / sigma with sigma^2 = 4 df sum |h~_k|^2 / S(f_k) over the waveform's bins kstart..k1
+    (float64, on the host: part of preparing the inputs, not of the search)."""
+    m1, m2, snr = (np.atleast_1d(np.asarray(x, np.float64)) for x in (m1, m2, snr))
+    df = fs / n
+    sig = np.empty(len(m1))
+    for c0 in range(0, len(m1), chunk):
+        b = synth.taylorf2_bank(m1[c0:c0 + chunk], m2[c0:c0 + chunk], n, fs, f_low)
+        for t in range(b.n_tmpl):
+            lo, hi = int(b.kstart[t]), int(b.k1[t])
+            h = b.spectrum(t)[lo:hi + 1]
+            psd = synth.aligo_psd_fit(np.arange(lo, hi + 1) * df)
+            sig[c0 + t] = np.sqrt(4.0 * df * np.sum(np.abs(h) ** 2 / psd))
+    return snr / sig
+
+
+def realisation_jobs(seeds, per_seg: int, n: int, cfg: int = CFG, mc_range=MC_RANGE, q_range=Q_RANGE,
+                     glitch_rate: float = GLITCH_RATE, margin: float = 8.0):
+    """Process-pool jobs (synth.realisation_job) of the two-detector realisations ``seeds``: each
+    with ``per_seg`` injections (network SNR 6-20 split equally between the detectors, L arrival
+    within +-10 ms) and their amplitude factors.  A generator: the amplitudes of a realisation are
+    computed when the pool asks for its job."""
+    for r in seeds:
+        ip = synth.realisation_params(cfg, r, n / FS, per_seg, mc_range, q_range, margin)
+        amp_h = injection_amplitudes(ip["m1"], ip["m2"], ip["snr_h"], n) if per_seg else np.empty(0)
+        amp_l = amp_h * (ip["snr_l"] / ip["snr_h"]) if per_seg else np.empty(0)
+        yield (r, cfg, n, FS, F_LOW, ip, amp_h, amp_l, glitch_rate)
+
+
 def injection_realisation(r: int, n: int, per_seg: int = 1, margin: float = 8.0):
-    """Realisation r: independent noise + glitches in both detectors with ``per_seg`` injections
-    (network SNR 6-20, split equally; L arrival within +-10 ms).  Returns (strain_h, strain_l,
-    params) with the parameter arrays of synth.injection_params."""
-    return synth.realisation(CFG, r, n, FS, F_LOW, per_seg, MC_RANGE, Q_RANGE, GLITCH_RATE, margin)
+    """Realisation r: independent noise + glitches in both detectors with ``per_seg`` injections.
+    Returns (strain_h, strain_l, params) with the parameter arrays of synth.injection_params."""
+    return synth.realisation_job(next(realisation_jobs([r], per_seg, n, margin=margin)))[1]

@@ -17,7 +17,8 @@ from .psd import aligo_psd_fit
 from .noise import coloured_noise
 from .bank import Bank, taylorf2_bank, mchirp_eta, bank_by_tau0, equal_mass_bank
 from .glitch import sine_gaussian_glitches
-from .inject import injection_strain, injection_params, realisation, realisation_job, single_threaded
+from .inject import (injection_strain, injection_params, realisation_params, realisation, realisation_job,
+                     single_threaded)
 from .strain import make_strain
 from .triggers import (TRIGGER_DTYPE, CANDIDATE_DTYPE, COINC_DTYPE,
                        synthetic_triggers, synthetic_candidates, synthetic_coincs,
@@ -27,7 +28,8 @@ __all__ = [
     "rng", "NOISE", "GLITCH", "INJECT", "BANK", "TRIG",
     "aligo_psd_fit", "coloured_noise", "Bank", "taylorf2_bank", "mchirp_eta",
     "bank_by_tau0", "equal_mass_bank", "sine_gaussian_glitches",
-    "injection_strain", "injection_params", "realisation", "realisation_job", "single_threaded",
+    "injection_strain", "injection_params", "realisation_params", "realisation", "realisation_job",
+    "single_threaded",
     "make_strain",
     "TRIGGER_DTYPE", "CANDIDATE_DTYPE", "COINC_DTYPE",
     "synthetic_triggers", "synthetic_candidates", "synthetic_coincs", "synthetic_coinc_set",

@@ -1,34 +1,27 @@
 """Compact-binary injections (TaylorF2, same signal model as the banks).
 
-Loudness is specified as the optimal SNR of the injected waveform in the
-ANALYTIC PSD of the synthetic noise (the standard way to label an injection);
-the search never sees this number - it normalises with its own PSD estimate.
+An injection is the TaylorF2 spectrum of ``synth.bank`` scaled by a plain amplitude factor
+``amp``.  The generator draws target SNRs (``injection_params``) but sets no loudness itself:
+turning a target SNR into ``amp`` needs an inner product against the PSD, which belongs to the
+callers (the oracle's in the tests, the workload's own in the benchmark and training scripts).
 """
 import numpy as np
 
 from .bank import taylorf2_bank, tau0, masses_from_mchirp_q, MSUN_SEC
-from .psd import aligo_psd_fit
 
 
 def injection_strain(n: int, fs: float, f_start: float, m1: float, m2: float, t_c: float,
-                     phi_c: float, snr: float, psd_fn=aligo_psd_fit) -> np.ndarray:
-    """Time series (float64, length n, circular) of one injection with optimal SNR ``snr``."""
-    return np.fft.irfft(injection_spectrum(n, fs, f_start, m1, m2, t_c, phi_c, snr, psd_fn), n=n) * fs
+                     phi_c: float, amp: float) -> np.ndarray:
+    """Time series (float64, length n, circular) of one injection of amplitude factor ``amp``."""
+    return np.fft.irfft(injection_spectrum(n, fs, f_start, m1, m2, t_c, phi_c, amp), n=n) * fs
 
 
 def injection_spectrum(n: int, fs: float, f_start: float, m1: float, m2: float, t_c: float,
-                       phi_c: float, snr: float, psd_fn=aligo_psd_fit, psd_grid=None) -> np.ndarray:
-    """One-sided spectrum (k = 0..n/2, complex128) of ``injection_strain``; ``psd_grid`` may
-    hold psd_fn at k fs / n for k >= 1 (index k) to avoid re-evaluating it."""
+                       phi_c: float, amp: float) -> np.ndarray:
+    """One-sided spectrum (k = 0..n/2, complex128) of ``injection_strain``: ``amp`` times the
+    TaylorF2 spectrum of the pair (coalescence at t_c, phase phi_c)."""
     b = taylorf2_bank([m1], [m2], n, fs, f_start, tc=[t_c], phic=[phi_c])
-    h = b.spectrum(0)
-    df = fs / n
-    lo, hi = int(b.kstart[0]), int(b.k1[0])
-    k = np.arange(lo, hi + 1)
-    psd = psd_grid[lo:hi + 1] if psd_grid is not None else psd_fn(k * df)
-    opt2 = 4.0 * df * np.sum(np.abs(h[lo:hi + 1]) ** 2 / psd)
-    h *= snr / np.sqrt(opt2)
-    return h
+    return b.spectrum(0) * amp
 
 
 def injection_params(count: int, gen: np.random.Generator, mc_min: float, mc_max: float,
@@ -57,29 +50,32 @@ def injection_params(count: int, gen: np.random.Generator, mc_min: float, mc_max
                 snr_l=rho / np.sqrt(2.0), tc_h=tc_h, tc_l=tc_h + dt, phi_h=ph_h, phi_l=ph_l)
 
 
-def realisation(cfg: int, r: int, n: int, fs: float, f_low: float, per_seg: int, mc_range, q_range,
-                glitch_rate: float, margin: float = 8.0):
-    """Two-detector realisation r of seed family cfg: independent noise and glitches with
-    ``per_seg`` injections (parameters from ``injection_params``, drawn from the stream
-    rng(cfg, 0, r, INJECT)).  Returns (strain_h, strain_l, params)."""
+def realisation_params(cfg: int, r: int, T: float, per_seg: int, mc_range, q_range, margin: float = 8.0):
+    """Injection parameters of two-detector realisation r of seed family cfg (``injection_params``
+    drawn from the stream rng(cfg, 0, r, INJECT); several per segment are spread over slots)."""
     from .seeds import rng, INJECT
+    return injection_params(per_seg, rng(cfg, 0, r, INJECT), mc_range[0], mc_range[1], q_range[0], q_range[1], T,
+                            margin=margin, slots=per_seg > 1)
+
+
+def realisation(cfg: int, r: int, n: int, fs: float, f_low: float, ip, amp_h, amp_l, glitch_rate: float):
+    """Two-detector realisation r of seed family cfg: independent noise and glitches with the
+    injections of ``ip`` (``realisation_params``) at amplitude factors amp_h / amp_l.  Returns
+    (strain_h, strain_l, ip)."""
     from .strain import make_strain
-    T = n / fs
-    ip = injection_params(per_seg, rng(cfg, 0, r, INJECT), mc_range[0], mc_range[1], q_range[0], q_range[1], T,
-                          margin=margin, slots=per_seg > 1)
     out = []
-    for det, key in ((0, "h"), (1, "l")):
+    for det, key, amp in ((0, "h", amp_h), (1, "l", amp_l)):
         injs = [dict(m1=ip["m1"][k], m2=ip["m2"][k], t_c=ip["tc_" + key][k], phi_c=ip["phi_" + key][k],
-                     snr=ip["snr_" + key][k]) for k in range(per_seg)]
+                     amp=amp[k]) for k in range(len(amp))]
         out.append(make_strain(cfg, det, r, n, fs, f_low, glitch_rate=glitch_rate, injections=injs)[0])
     return out[0], out[1], ip
 
 
 def realisation_job(args):
-    """Process-pool entry: (r, per_seg, cfg, n, fs, f_low, mc_range, q_range, glitch_rate) ->
-    (r, realisation(...)).  Lives here so spawned workers import only numpy and synth."""
-    r, per_seg, cfg, n, fs, f_low, mc, q, glitch = args
-    return r, realisation(cfg, r, n, fs, f_low, per_seg, mc, q, glitch)
+    """Process-pool entry: (r, cfg, n, fs, f_low, ip, amp_h, amp_l, glitch_rate) -> (r, realisation(...)).
+    Lives here so spawned workers import only numpy and synth."""
+    r, cfg, n, fs, f_low, ip, amp_h, amp_l, glitch = args
+    return r, realisation(cfg, r, n, fs, f_low, ip, amp_h, amp_l, glitch)
 
 
 def single_threaded():

@@ -13,20 +13,16 @@ def make_strain(cfg: int, det: int, seg: int, n: int, fs: float, f_low: float,
                 noise: bool = True):
     """Return (float32 strain [n], info dict).
 
-    ``injections`` is a sequence of dicts with keys m1, m2, t_c, phi_c, snr.
+    ``injections`` is a sequence of dicts with keys m1, m2, t_c, phi_c, amp (the factor on the
+    TaylorF2 spectrum, see ``inject``).
     Noise is high-passed at 0.75 f_low.  Noise and injections are summed in the frequency
     domain and transformed once; glitches are added in the time domain.
     """
     spec = np.zeros(n // 2 + 1, dtype=np.complex128)
     if noise:
         spec += coloured_noise_spectrum(n, fs, rng(cfg, det, seg, NOISE), 0.75 * f_low, psd_fn)
-    if len(injections):
-        grid = np.empty(n // 2 + 1)
-        grid[1:] = psd_fn(np.arange(1, n // 2 + 1) * (fs / n))
-        grid[0] = grid[1]
-        for inj in injections:
-            spec += injection_spectrum(n, fs, f_low, inj["m1"], inj["m2"], inj["t_c"], inj["phi_c"],
-                                       inj["snr"], psd_fn, grid)
+    for inj in injections:
+        spec += injection_spectrum(n, fs, f_low, inj["m1"], inj["m2"], inj["t_c"], inj["phi_c"], inj["amp"])
     s = np.fft.irfft(spec, n=n) * fs
     glitches = []
     if glitch_rate > 0:

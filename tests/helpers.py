@@ -20,6 +20,23 @@ def analytic_psd(n, fs):
     return p
 
 
+def loud(injections, n, fs, f_low):
+    """Injection dicts with a target SNR (keys m1, m2, t_c, phi_c, snr) as synth wants them (amp in
+    place of snr): the amplitude factor is snr / sigma, sigma the oracle's template sigma of the
+    injected waveform in the analytic PSD over its band."""
+    import oracle
+    psd = analytic_psd(n, fs)
+    out = []
+    for inj in injections:
+        b = synth.taylorf2_bank([inj["m1"]], [inj["m2"]], n, fs, f_low)
+        a, c = oracle.band_edges(n, fs, f_low, b.kstart[0], b.k1[0])
+        sigma = oracle.template_sigma(b.spectrum(0), psd, n, fs, a, c)
+        d = {k: v for k, v in inj.items() if k != "snr"}
+        d["amp"] = inj["snr"] / sigma
+        out.append(d)
+    return out
+
+
 def device_bank(ctx, bank, psd_dev, f_low, dtype="f32"):
     """Prepare a synth.Bank on the device through hs_prepare_bank."""
     import torch

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import DELTA, analytic_psd
+from helpers import DELTA, analytic_psd, loud
 from search_compare import check_followed, check_stage, compare_coincs, exact_coinc, oracle_series
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
@@ -47,8 +47,8 @@ def world():
     coarse = synth.taylorf2_bank(cm1, cm2, N // 4, FS / 4, F_LOW)
     t = 150
     inj = lambda tc, ph: [dict(m1=fm1[t], m2=fm2[t], t_c=tc, phi_c=ph, snr=11.0)]
-    sh = synth.make_strain(81, 0, 0, N, FS, F_LOW, glitch_rate=0.05, injections=inj(131.0, 0.4))[0]
-    sl = synth.make_strain(81, 1, 0, N, FS, F_LOW, glitch_rate=0.05, injections=inj(131.006, 2.0))[0]
+    sh = synth.make_strain(81, 0, 0, N, FS, F_LOW, glitch_rate=0.05, injections=loud(inj(131.0, 0.4), N, FS, F_LOW))[0]
+    sl = synth.make_strain(81, 1, 0, N, FS, F_LOW, glitch_rate=0.05, injections=loud(inj(131.006, 2.0), N, FS, F_LOW))[0]
     psd = analytic_psd(N, FS)
     d = ctx.device
     psd_d = torch.as_tensor(psd, device=d)

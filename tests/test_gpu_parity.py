@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import DELTA, analytic_psd, check_candidates, device_bank
+from helpers import DELTA, analytic_psd, check_candidates, device_bank, loud
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +32,8 @@ def ctx():
 
 
 def _strain(cfg, det, n, fs, f_low, **kw):
+    if "injections" in kw:
+        kw["injections"] = loud(kw["injections"], n, fs, f_low)
     s, _ = synth.make_strain(cfg, det, 0, n, fs, f_low, **kw)
     return s
 

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import synth
 from oracle import proposer as P
-from helpers import DELTA
+from helpers import DELTA, loud
 from search_compare import check_followed, check_stage, cols, compare_coincs, exact_coinc, oracle_series
 
 pytestmark = pytest.mark.gpu
@@ -237,9 +237,9 @@ def test_hierarchical_search_matches_oracle_end_to_end(ctx, use_proposer, n_seg)
     coarse = synth.taylorf2_bank(m1[::6], m2[::6], n // 4, fs / 4, f_low)
     t = 24
     last = n_seg - 1
-    sh = [synth.make_strain(78, 0, s, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)]
+    sh = [synth.make_strain(78, 0, s, n, fs, f_low, injections=loud([dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)], n, fs, f_low)
                             if s == last else [])[0] for s in range(n_seg)]
-    sl = [synth.make_strain(78, 1, s, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)]
+    sl = [synth.make_strain(78, 1, s, n, fs, f_low, injections=loud([dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)], n, fs, f_low)
                             if s == last else [])[0] for s in range(n_seg)]
     psd = analytic_psd(n, fs)
     d = ctx.device
@@ -349,7 +349,7 @@ def test_flat_search_matches_oracle_end_to_end(ctx, n_seg):
     m1, m2 = synth.bank_by_tau0(40, 4.0, 10.0, 1.0, 3.0, g)
     fine = synth.taylorf2_bank(m1, m2, n, fs, f_low)
     t, last = 17, n_seg - 1
-    inj = lambda s, tc, ph: [dict(m1=m1[t], m2=m2[t], t_c=tc, phi_c=ph, snr=11.0)] if s == last else []
+    inj = lambda s, tc, ph: loud([dict(m1=m1[t], m2=m2[t], t_c=tc, phi_c=ph, snr=11.0)], n, fs, f_low) if s == last else []
     sh = [synth.make_strain(79, 0, s, n, fs, f_low, glitch_rate=0.3, injections=inj(s, 5.0, 0.3))[0]
           for s in range(n_seg)]
     sl = [synth.make_strain(79, 1, s, n, fs, f_low, glitch_rate=0.3, injections=inj(s, 5.004, 1.3))[0]

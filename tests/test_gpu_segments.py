@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import DELTA
+from helpers import DELTA, loud
 from oracle import segments as S
 from search_compare import check_followed, check_stage, cols, compare_coincs, exact_coinc, oracle_series
 
@@ -42,8 +42,8 @@ def world():
     t_inj = (starts[1] + PAD_LO + 10 * 2048) / FS
     assert starts[0] + N - PAD_HI <= t_inj * FS < starts[0] + N
     inj = lambda dt, ph: [dict(m1=fm1[t], m2=fm2[t], t_c=t_inj + dt, phi_c=ph, snr=12.0)]
-    bh = synth.make_strain(82, 0, 0, BLOCK, FS, F_LOW, glitch_rate=0.05, injections=inj(0.0, 0.4))[0]
-    bl = synth.make_strain(82, 1, 0, BLOCK, FS, F_LOW, glitch_rate=0.05, injections=inj(0.005, 1.9))[0]
+    bh = synth.make_strain(82, 0, 0, BLOCK, FS, F_LOW, glitch_rate=0.05, injections=loud(inj(0.0, 0.4), BLOCK, FS, F_LOW))[0]
+    bl = synth.make_strain(82, 1, 0, BLOCK, FS, F_LOW, glitch_rate=0.05, injections=loud(inj(0.005, 1.9), BLOCK, FS, F_LOW))[0]
     d = ctx.device
     # per-block PSD: the GPU's Welch over the whole block on the block's grid, every 2nd bin is the
     # segment grid; against the oracle's block PSD on the segment grid

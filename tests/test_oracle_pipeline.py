@@ -5,6 +5,7 @@ import numpy as np
 
 import oracle
 import synth
+from helpers import loud
 
 
 def test_flat_and_hierarchical_find_a_loud_injection():
@@ -17,8 +18,8 @@ def test_flat_and_hierarchical_find_a_loud_injection():
     t = 30
     inj_h = dict(m1=m1[t], m2=m2[t], t_c=9.0, phi_c=0.3, snr=11.0)
     inj_l = dict(m1=m1[t], m2=m2[t], t_c=9.004, phi_c=1.3, snr=11.0)
-    sh, _ = synth.make_strain(77, 0, 0, n, fs, f_low, injections=[inj_h])
-    sl, _ = synth.make_strain(77, 1, 0, n, fs, f_low, injections=[inj_l])
+    sh, _ = synth.make_strain(77, 0, 0, n, fs, f_low, injections=loud([inj_h], n, fs, f_low))
+    sl, _ = synth.make_strain(77, 1, 0, n, fs, f_low, injections=loud([inj_l], n, fs, f_low))
     k = np.arange(n // 2 + 1)
     psd = np.empty(n // 2 + 1)
     psd[1:] = synth.aligo_psd_fit(k[1:] * fs / n)
@@ -43,8 +44,8 @@ def test_proposer_with_every_cell_selected_reproduces_the_plain_hierarchy():
     fine = synth.taylorf2_bank(m1, m2, n, fs, f_low)
     coarse = synth.taylorf2_bank(m1[::6], m2[::6], n // 4, fs / 4, f_low)
     t = 24
-    sh, _ = synth.make_strain(78, 0, 0, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)])
-    sl, _ = synth.make_strain(78, 1, 0, n, fs, f_low, injections=[dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)])
+    sh, _ = synth.make_strain(78, 0, 0, n, fs, f_low, injections=loud([dict(m1=m1[t], m2=m2[t], t_c=7.0, phi_c=0.3, snr=10.0)], n, fs, f_low))
+    sl, _ = synth.make_strain(78, 1, 0, n, fs, f_low, injections=loud([dict(m1=m1[t], m2=m2[t], t_c=7.003, phi_c=1.0, snr=10.0)], n, fs, f_low))
     k = np.arange(n // 2 + 1)
     psd = np.empty(n // 2 + 1)
     psd[1:] = synth.aligo_psd_fit(k[1:] * fs / n)

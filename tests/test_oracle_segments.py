@@ -6,6 +6,7 @@ import scipy.signal
 
 import oracle
 import synth
+from helpers import loud
 from oracle import segments as S
 
 
@@ -92,8 +93,9 @@ def test_block_search_finds_an_injection_once_on_the_valid_timeline():
     m1, m2 = synth.equal_mass_bank([9.0, 12.0, 15.0])
     t_inj = 25.3                                    # block time (s): inside segments 1 and 2
     inj = [dict(m1=12.0, m2=12.0, t_c=t_inj, phi_c=0.3, snr=14.0)]
-    bh = synth.make_strain(903, 0, 0, L, fs, f_low, injections=inj)[0]
-    bl = synth.make_strain(903, 1, 0, L, fs, f_low, injections=[dict(inj[0], t_c=t_inj + 0.004, phi_c=1.2)])[0]
+    bh = synth.make_strain(903, 0, 0, L, fs, f_low, injections=loud(inj, L, fs, f_low))[0]
+    bl = synth.make_strain(903, 1, 0, L, fs, f_low,
+                           injections=loud([dict(inj[0], t_c=t_inj + 0.004, phi_c=1.2)], L, fs, f_low))[0]
     starts = S.segment_starts(L, n, pad_lo, pad_hi)
     covering = [st for st in starts if st <= t_inj * fs < st + n]
     assert len(covering) == 2
