@@ -2,11 +2,12 @@
 //
 // Sec. II down-weights triggers with the chi-square test it cites; the test splits the template
 // band into p bins of equal template power and compares each bin's share of the complex SNR with
-// 1/p of the total.  Only triggers at or above rho_min are tested: they are compacted first, then
-// one workgroup per (trigger, bin) evaluates the band-limited SNR z_l at the trigger's sample by
-// a direct sum over the bin (float64 phasor recurrence and accumulation), and a last kernel forms
-// chi2, the per-bin terms and the re-weighted SNR.  Splitting by bin gives p workgroups per
-// trigger, enough to fill the GPU when only a few hundred triggers need the test.
+// 1/p of the total.  Only triggers at or above rho_min are tested: they are compacted first and
+// gathered into groups of up to CQ_GROUP triggers of one template; the band-limited SNRs z_l at
+// the triggers' samples are direct sums over each bin (Horner's rule in float64, one pass over the
+// bin's template elements per group; see chisq_bin_sums), and a last kernel forms chi2, the
+// per-bin terms and the re-weighted SNR.  Splitting by bin gives p workgroups per four groups,
+// enough to fill the GPU when only a few hundred triggers need the test.
 #include <cmath>
 
 #include "dft.h"

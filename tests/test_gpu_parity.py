@@ -41,8 +41,12 @@ def _strain(cfg, det, n, fs, f_low, **kw):
 # ------------------------------------------------------------------------------------------
 # a1: whitening and Welch PSD
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("n,fs,f_low", [(2 ** 13, 512.0, 30.0), (2 ** 16, 2048.0, 20.0), (2 ** 19, 2048.0, 20.0)])
+@pytest.mark.parametrize("n,fs,f_low", [(2 ** 10, 128.0, 10.3), (2 ** 13, 512.0, 30.0), (2 ** 16, 2048.0, 20.0),
+                                        (2 ** 19, 2048.0, 20.0), (2 ** 22, 2048.0, 20.0)])
 def test_whiten_matches_oracle(ctx, n, fs, f_low):
+    """The real-input transform (n/2-point complex transform of the sample pairs, recombined) and
+    the whitening against the oracle, from the smallest length to the largest, with f_low n / fs
+    on and between bins."""
     import torch
     from paper_2309_00019_amd import hs
     _say(f"whiten n={n}")
