@@ -654,6 +654,53 @@ def test_chisq_every_group_size_matches_oracle(ctx):
     assert np.any(otr["chisq"] > 2.0) and np.any(otr["chisq"] < 1.0)
 
 
+@pytest.mark.parametrize("at_peaks", [False, True])
+def test_chisq_unsorted_bank_far_apart_groups_match_oracle(ctx, at_peaks):
+    """Consecutive groups of a workgroup's four far apart in frequency (an unsorted bank that
+    alternates light and heavy templates, so a bin's union spans most of the band with gaps that
+    skip whole windows), against the oracle's chi-square at hand-placed samples, in both entry
+    points (at the peaks the triggers carry the oracle's own z)."""
+    import torch
+    from paper_2309_00019_amd import hs
+    _say(f"chisq unsorted bank at_peaks={at_peaks}")
+    n, fs, f_low = 2 ** 16, 2048.0, 20.0
+    masses = [1.4, 28.0, 2.2, 30.0, 1.6, 22.0, 3.5, 26.0, 1.8, 18.0]
+    m1, m2 = synth.equal_mass_bank(np.asarray(masses))
+    bank = synth.taylorf2_bank(m1, m2, n, fs, f_low)
+    s = _strain(23, 0, n, fs, f_low, glitch_rate=0.3)
+    psd = analytic_psd(n, fs)
+    psd_d = torch.as_tensor(psd, device=ctx.device)
+    pb = device_bank(ctx, bank, psd_d, f_low)
+    spec = hs.hs_whiten(ctx, torch.as_tensor(s, device=ctx.device), fs, f_low, psd_d)
+    st = oracle.strain_fft(s, fs)
+    # the filter's own z at the chosen samples (what its triggers carry; at the peaks the widest
+    # bin is formed from it); the oracle's chi-square does not use it
+    zs = hs.hs_snr_series(ctx, spec, n, fs, pb, torch.arange(bank.n_tmpl, dtype=torch.int32,
+                                                              device=ctx.device)).cpu().numpy()
+    rng = np.random.default_rng(23)
+    tps, t0 = 25, 7000
+    rows = []
+    for t in range(bank.n_tmpl):
+        for m in np.sort(rng.choice(n, 1 + (t * 3) % 7, replace=False)):
+            z = zs[t][m]
+            rows.append((0, t, t0 + int(m) * tps, float(abs(z)) + (0.0 if at_peaks else 6.0), float(np.angle(z))))
+    rec = np.array(rows, dtype=hs.TRIGGER)
+    if at_peaks:   # rho and arg z of the filter's series; rho_min = 1 selects nearly all
+        rec = rec[rec["snr"] >= 1.0]
+    trig = hs.to_device_records(rec, ctx.device)
+    rho_min = 1.0 if at_peaks else 5.0
+    chi, rw, bins = hs.hs_chisq(ctx, spec, n, fs, pb, trig, seg_t0=t0, ticks_per_sample=tps, rho_min=rho_min,
+                                bins=True, at_peaks=at_peaks)
+    chi, bins = chi.cpu().numpy(), bins.cpu().numpy()
+    otr = oracle.pipeline.reweight_triggers({k: rec[k] for k in ("tmpl", "tick", "snr")}, st, psd, n, fs, f_low,
+                                            bank, 8, rho_min, tps, t0)
+    assert len(rec) >= 15
+    for i in range(len(rec)):
+        c_ref = otr["chisq"][i]
+        assert abs(chi[i] - c_ref) <= 1e-3 * (1.0 + c_ref), (i, int(rec["tmpl"][i]), chi[i], c_ref)
+        assert np.all(np.abs(bins[i] - otr["bins"][i]) <= 1e-3 * (1.0 + 14.0 * c_ref)), (i, bins[i], otr["bins"][i])
+
+
 def test_exact_capacity_holds_unevenly_spread_candidates(ctx):
     """Candidates concentrated in time (a loud glitch, two templates) must fit a capacity equal
     to their count: the striped lists spill instead of overflowing."""
