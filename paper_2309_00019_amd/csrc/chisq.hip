@@ -125,23 +125,6 @@ __device__ __forceinline__ void horner_step(float2 q, const double *sr, const do
     }
 }
 
-// z_l for one (bin l, group of active triggers of one template): sum over the bins of l of
-// q_k exp(+2 pi i k m / N), q_k = d~_k conj(w~_k) formed once per bin in float32 and shared by the
-// group's triggers; everything after it in float64.
-//
-// A workgroup takes bin l of CQ_WAVES consecutive groups, one wavefront each.  The bank is sorted
-// by chirp mass, so their bins cover nearly the same bins k, and the data spectrum is staged once
-// for all of them: the union of their ranges is cut into rows of 64 bins from its lowest bin kb,
-// lane L of every wavefront owns the bins kb + L + 64 r, and windows of CQ_ROWS rows are staged
-// in LDS (double-buffered) from the top down.  Each wavefront reads only its own template from
-// HBM.  With v = exp(2 pi i m / N), q = 0 outside the bin and kw = kb + 64 r0 the first bin of
-// the lowest window that meets the bin (row r0),
-//     z_l = v^kw sum_L v^L P_L(v^64),   P_L(w) = sum_{r >= r0} q(kb + L + 64 r) w^(r - r0).
-// Each lane evaluates its P by Horner's rule over the rows (one complex multiply-add per bin and
-// trigger), the sum over lanes is a tree whose level s joins blocks of 2^s lanes with the factor
-// v^(2^s), and v^kw is applied last.  Every power
-// of v used is an exact float64 sincospi of (E m mod N) / N, computed once per wavefront (one per
-// lane), so no twiddle table is read; v^64 is the same in every lane and lives in scalar registers.
 // The widest of a template's p bins (the lowest index among equals).  The bins partition the
 // band over which the filter forms z, so sum_l z_l = z; for triggers that carry the filter's own
 // rho and arg z, the widest bin's sum is formed as z minus the others instead of being read.
@@ -199,9 +182,9 @@ __device__ __forceinline__ void run_windows(const WinCtx &c, float2 (*win)[CQ_RO
     constexpr int SR = (R + NW - 1) / NW;  // rows each wavefront stages: wv, wv + NW, ... (below R)
     float2 dn[SR];
     typename ST::elem tc[R], tn[R];
-    // (a wavefront whose row is past the window loads the window's last row and does not store it,
-    // so every wavefront issues the same loads on every trip)
-    // bins fit in 32 bits (n <= 2^22): offsets from scalar bases
+    // Bins fit in 32 bits (n <= 2^22): offsets from scalar bases.  A wavefront whose row is past
+    // the window loads the window's last row and does not store it, so every wavefront issues the
+    // same loads on every trip.
     const int32_t kmax = (int32_t)(c.n / 2 - 1);
     auto stage = [&](int64_t wi) {
         const int32_t k0 = (int32_t)(c.kb + 64 * wi * R);
@@ -271,6 +254,24 @@ __device__ __forceinline__ void run_windows(const WinCtx &c, float2 (*win)[CQ_RO
     }
 }
 
+// z_l for one (bin l, group of active triggers of one template): sum over the bins of l of
+// q_k exp(+2 pi i k m / N), q_k = d~_k conj(w~_k) formed once per bin in float32 and shared by the
+// group's triggers; everything after it in float64.
+//
+// A workgroup takes bin l of CQ_WAVES consecutive groups, one wavefront each.  The bank is sorted
+// by chirp mass, so their bins cover nearly the same bins k, and the data spectrum is staged once
+// for all of them: the union of their ranges is cut into rows of 64 bins from its lowest bin kb,
+// lane L of every wavefront owns the bins kb + L + 64 r, and windows of CQ_ROWS rows are staged
+// in LDS (double-buffered) from the top down.  Each wavefront reads only its own template from
+// HBM.  With v = exp(2 pi i m / N), q = 0 outside the bin and kw = kb + 64 r0 the first bin of
+// the lowest window that meets the bin (row r0),
+//     z_l = v^kw sum_L v^L P_L(v^64),   P_L(w) = sum_{r >= r0} q(kb + L + 64 r) w^(r - r0).
+// Each lane evaluates its P by Horner's rule over the rows (one complex multiply-add per bin and
+// trigger), the sum over lanes is a tree whose level s joins blocks of 2^s lanes with the factor
+// v^(2^s), and v^kw is applied last.  Every power of v used is an exact float64 sincospi of
+// (E m mod N) / N, computed once per wavefront (one per lane), so no twiddle table is read; v^64
+// is the same in every lane and lives in scalar registers.  Any bank order gives the same sums;
+// the sorted order only keeps the unions, and so the staged rows, short.
 template <typename ST>
 __global__ __launch_bounds__(64 * CQ_WAVES) void chisq_bin_sums(
     const float2 *__restrict__ dspec, int64_t n, const typename ST::elem *__restrict__ spectra,
