@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64 * CQ_WAVES) void chisq_bin_sums(
     const int64_t n_win = top > kb ? (top - 1 - kb) / (64 * R) + 1 : 0;  // the same in every wavefront
     // the windows this wavefront steps; its polynomial starts at the first row of w_lo
     const int64_t w_lo = reads ? (b0 - kb) / (64 * R) : 1, w_hi = reads ? (b1 - 1 - kb) / (64 * R) : 0;
-    const int64_t kw = kb + 64 * R * w_lo;
+    const int64_t kw = reads ? kb + 64 * R * w_lo : 0;  // kb is INT64_MAX when no wavefront reads
     if (reads && lane < 8 * g) {
         const int j = lane >> 3, s = lane & 7;
         const uint64_t m = msamp[a0 + j];
