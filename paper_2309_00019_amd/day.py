@@ -187,13 +187,18 @@ def main():
                 rec = hs.as_records(tr, hs.TRIGGER)
                 sel = rec["tmpl"] % args.subset_every == 0
                 sub[det] = rec[sel]
+            # the search's own coincidence geometry, in ticks
+            tk = cfg.ticks_per_second
+            geom = dict(n_slides=cfg.n_slides, step=int(round(cfg.step_sec * tk)),
+                        window=int(round(cfg.coinc_window_sec * tk)), wrap=n_seg * search.timeline(cfg, n)[3],
+                        cluster_w=int(round(cfg.cluster_sec * tk)))
             co, bg = hs.hs_timeslide_coinc(ctx, hs.to_device_records(sub["h"], dev), hs.to_device_records(sub["l"], dev),
-                                           30000, cfg.n_slides, int(round(cfg.step_sec * 51200)), 768,
-                                           n_seg * n * 25, 51200, np.asarray(EDGES, np.float32), min_snr_c=7.0)
+                                           fine_h.n_tmpl, geom["n_slides"], geom["step"], geom["window"], geom["wrap"],
+                                           geom["cluster_w"], np.asarray(EDGES, np.float32),
+                                           min_snr_c=cfg.coinc_min_snr)
             c = hs.as_records(co, hs.COINC)
             np.savez(args.save_subset, trig_h=sub["h"], trig_l=sub["l"], coincs=c, bg_counts=bg,
-                     edges=np.asarray(EDGES, np.float32), n_slides=cfg.n_slides, step=5120, window=768,
-                     wrap=n_seg * n * 25, cluster_w=51200, min_snr_c=7.0)
+                     edges=np.asarray(EDGES, np.float32), ticks_per_second=tk, min_snr_c=cfg.coinc_min_snr, **geom)
             log(f"[day] subset of {len(sub['h'])} + {len(sub['l'])} triggers, {len(c)} coincidences saved")
         runs[key] = (None, far)           # only the fit is needed from here on
         del res

@@ -29,10 +29,11 @@ def main(path):
     edges = z["edges"]
     K, step, window, wrap, cw = (int(z[k]) for k in ("n_slides", "step", "window", "wrap", "cluster_w"))
     floor = float(z["min_snr_c"])
+    tk = int(z["ticks_per_second"])
     t0 = time.perf_counter()
     ref = oracle.timeslide_coinc(dict(tmpl=th["tmpl"].astype(np.int64), tick=th["tick"], snr=th["snr"]),
                                  dict(tmpl=tl["tmpl"].astype(np.int64), tick=tl["tick"], snr=tl["snr"]),
-                                 K, step, window, wrap, cw, edges, 51200, min_snr_c=floor)
+                                 K, step, window, wrap, cw, edges, tk, min_snr_c=floor)
     secs = time.perf_counter() - t0
     c = ref["coincs"]
     same = len(gc) == len(c["slide"])
@@ -40,7 +41,7 @@ def main(path):
         same = same and np.array_equal(gc[f].astype(np.int64), np.asarray(c[f], np.int64))
     same = same and np.array_equal(gc["stat"], np.asarray(c["stat"], np.float32))
     counts_same = bool(np.array_equal(z["bg_counts"], ref["bg_counts"]))
-    t_b = K * wrap / 51200.0
+    t_b = K * wrap / tk
     out = {"templates": int(len(np.unique(th["tmpl"]))), "triggers": [int(len(th)), int(len(tl))],
            "coincidences": [int(len(gc)), int(len(c["slide"]))], "records_identical": bool(same),
            "bg_counts_identical": counts_same, "oracle_seconds": round(secs, 1),
