@@ -10,7 +10,7 @@ its 16 features (hs_proposer_features) and, as the target, the neighbourhood cel
 injected (Mc, q).  The MLP is trained with Adam (hs_mlp_train_step); P is then the smallest
 value on a grid whose selected cells contain the injected cell for at least ``--hit`` of the
 held-out injections.  The plain +-frac chirp-mass rule, which the cells partition, is reported
-beside it as the judge.  Host workers only generate the synthetic strain.
+beside it as the yardstick.  Host workers only generate the synthetic strain.
 """
 import argparse
 import json
