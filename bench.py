@@ -168,7 +168,7 @@ def host_description():
 
 def cpu_baseline(args, synth, n, fs, f_low, strain_h, m1, m2, ctx=None, all_cores=True, strain_l=None, cfg=None):
     """The FP64 oracle's matched filter on a bounded sample of the same workload (host cores):
-    one core in this process, then every usable core (at most 16, the machine's CPU share) as a
+    one core in this process, then every usable core (at most 16 processes) as a
     pool of spawned processes each running the unchanged oracle on its share of the templates.
     With the L strain and the search configuration it also times the oracle's whole flat
     pipeline (both detectors: filter, clustering, chi-square re-weighting, coincidence over the
