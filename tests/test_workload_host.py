@@ -4,7 +4,8 @@ The injection amplitude factors that the benchmark's campaign, the proposer's tr
 the day run use (``workload.injection_amplitudes``: snr / sigma in the analytic PSD of the
 synthetic noise) against the oracle's template sigma (Sec. II, Eq. (2) with x = y = h) over the
 oracle's band of each waveform.  The two are written independently and must agree to rounding,
-for light systems whose band runs to Nyquist and heavy ones cut at ISCO.
+for light systems whose band runs to Nyquist and heavy ones cut at ISCO.  And the timeline of
+overlapping segments (Sec. V): where each segment's valid samples lie in ticks.
 """
 import numpy as np
 import pytest
@@ -29,3 +30,19 @@ def test_injection_amplitudes_equal_snr_over_oracle_sigma(n, fs):
         a, c = oracle.band_edges(n, fs, f_low, b.kstart[t], b.k1[t])
         sigma = oracle.template_sigma(b.spectrum(t), psd, n, fs, a, c)
         assert amp[t] * sigma == pytest.approx(snr[t], rel=1e-12)
+
+
+def test_timeline_of_overlapping_segments():
+    """Sample m of segment s lies at tick s * share + (m - pad_lo) * ticks_per_sample: 512 s
+    segments at 2048 Hz with 144 s / 16 s pads share 352 s of the timeline each; pads that are
+    negative, fill the segment or are not multiples of the stage-1 decimation are refused."""
+    from paper_2309_00019_amd import search
+    n = 2 ** 20
+    cfg = search.SearchConfig(pad_lo_sec=144.0, pad_hi_sec=16.0)
+    tpt, plo, phi, share = search.timeline(cfg, n)
+    assert (tpt, plo, phi) == (25, 144 * 2048, 16 * 2048)
+    assert share == 352 * 51200
+    assert search.timeline(search.SearchConfig(), n) == (25, 0, 0, n * 25)
+    for lo, hi in ((-1.0, 0.0), (256.0, 256.0), (144.0 + 1.0 / 2048, 16.0)):
+        with pytest.raises(ValueError):
+            search.timeline(search.SearchConfig(pad_lo_sec=lo, pad_hi_sec=hi), n)
