@@ -222,7 +222,9 @@ int hs_matched_filter(hs_ctx *ctx, const void *spec, int64_t n, double fs, const
  * n_ids records of 32 B and 36 KB of twiddles; HS_EINVAL when these leave no
  * room for one template's 8 n-byte intermediate (at n = 2^19 with 1,000
  * templates cap may reach about 1.96 M), or when the context's device is
- * beyond 63.
+ * beyond 63.  Like hs_matched_filter it synchronises its stream to return
+ * n_cand, so the call itself cannot be recorded into a graph: it serves code
+ * around a capture, not inside one.
  * Every allocation-free call on one GPU shares that GPU's array and leaves
  * its contents behind (counters are cleared at the start of each call):
  * calls that overlap on one GPU (other streams, threads or contexts) race and
