@@ -659,7 +659,8 @@ def test_chisq_unsorted_bank_far_apart_groups_match_oracle(ctx, at_peaks):
     """Consecutive groups of a workgroup's four far apart in frequency (an unsorted bank that
     alternates light and heavy templates, so a bin's union spans most of the band with gaps that
     skip whole windows), against the oracle's chi-square at hand-placed samples, in both entry
-    points (at the peaks the triggers carry the oracle's own z)."""
+    points (at the peaks the triggers carry the oracle's own z), including the segment's first and
+    last samples."""
     import torch
     from paper_2309_00019_amd import hs
     _say(f"chisq unsorted bank at_peaks={at_peaks}")
@@ -681,7 +682,10 @@ def test_chisq_unsorted_bank_far_apart_groups_match_oracle(ctx, at_peaks):
     tps, t0 = 25, 7000
     rows = []
     for t in range(bank.n_tmpl):
-        for m in np.sort(rng.choice(n, 1 + (t * 3) % 7, replace=False)):
+        ms = rng.choice(n, 1 + (t * 3) % 7, replace=False)
+        if t < 2:   # the segment's first and last samples (the powers of v wrap there)
+            ms = np.union1d(ms, [0, n - 1])
+        for m in np.sort(ms):
             z = zs[t][m]
             rows.append((0, t, t0 + int(m) * tps, float(abs(z)) + (0.0 if at_peaks else 6.0), float(np.angle(z))))
     rec = np.array(rows, dtype=hs.TRIGGER)
